@@ -1,0 +1,242 @@
+"""Plain FP64 reference of one RK4IP step of the coupled multimode NLSE.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): used by tests, the
+smoke check and the benchmark's CPU baseline; never by the library.
+
+What it computes, following Brehler et al., "Simulation of Nonlinear Signal
+Propagation in Multimode Fibers on Multi-GPU Systems" (CPC):
+
+* the linear operator of Eq. (1): attenuation plus the Taylor series of the
+  propagation constant, applied in the frequency domain (Section 3.1);
+* the Kerr term in the general tensor form N_p = i*gamma*sum_{l,m,n}
+  S_plmn A_l A_m conj(A_n) of the multimode NLSE the paper cites in Section 2
+  (for one mode it is the paper's gamma*|A|^2*A);
+* the RK4IP step of Eq. (6a-f) with separation distance z' = z + h/2
+  (Section 3.2, Eq. 5).
+
+Readings of the paper taken here (each is also a test below):
+
+* Eq. (6b) prints its brackets garbled; k1 is read as the half-step linear
+  propagator applied to h*N(A(z)), as Eq. (5) with z' = z+h/2 implies.
+* Fourier convention: numpy's forward kernel exp(-i w t).  The time-domain
+  operator i * (i^n/n!) beta_n d^n/dt^n then becomes i beta_n (-w)^n / n! per
+  angular frequency w, the Nyquist bin taking numpy's negative frequency.
+* A_out[p] is the output index of S, the last index n is the conjugated one.
+
+Pins (tests/test_oracle_pins.py, all CPU):
+
+* linear operator vs analytic derivatives of a Gaussian (every beta_n sign);
+* beta1 shift by an integer number of samples equals a circular roll;
+* beta2 broadening of a Gaussian vs the textbook closed form;
+* single-entry S tensors and linearity in S (index wiring, conjugated index);
+* power conservation exactly for the pair-exchange symmetry S_plmn = S_lpnm;
+* rank-1 S = u x u x u x u closed-form solution;
+* self-phase modulation exp(i gamma |A|^2 z) and CW + beta0 phase (IP frame);
+* classical RK4 reduction when the linear operator vanishes;
+* fundamental soliton and 4th-order convergence under step halving;
+* packed symmetric Kerr == generic Kerr for symmetric S.
+
+Units: t in ps, z in km, power in W, w in rad/ps, beta_n in ps^n/km.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+__all__ = [
+    "time_grid", "angular_frequencies", "linear_operator", "half_step_propagator",
+    "apply_linear", "KerrGeneric", "KerrPacked", "kerr_term", "rk4ip_step",
+    "propagate", "power", "step_doubling_estimate",
+]
+
+
+# ----------------------------------------------------------------------------
+# grids and the linear part (Eq. 1, operator L)
+# ----------------------------------------------------------------------------
+
+def time_grid(T: int, dt: float) -> np.ndarray:
+    """Sample times t_j = (j - T/2) dt."""
+    return (np.arange(T) - T // 2) * dt
+
+
+def angular_frequencies(T: int, dt: float) -> np.ndarray:
+    """w_k = 2 pi fftfreq(T, dt)[k] in rad/ps (numpy bin order)."""
+    return 2.0 * np.pi * np.fft.fftfreq(T, dt)
+
+
+def linear_operator(omega: np.ndarray, beta: np.ndarray, alpha: np.ndarray | None) -> np.ndarray:
+    """L(w) per mode, Eq. (1): -alpha/2 + i sum_n beta_n (-w)^n / n!.
+
+    With the forward kernel exp(-i w t), d/dt acts as multiplication by i w,
+    so the time-domain term i (i^n / n!) beta_n d^n/dt^n becomes
+    i (i * i w)^n beta_n / n! = i beta_n (-w)^n / n!.
+    ``beta`` is [M, n_beta]; returns [M, T] complex128.
+    """
+    beta = np.atleast_2d(np.asarray(beta, dtype=np.float64))
+    M, nb = beta.shape
+    L = np.zeros((M, omega.size), dtype=np.complex128)
+    for n in range(nb):
+        L += 1j * beta[:, n:n + 1] * (-omega[None, :]) ** n / math.factorial(n)
+    if alpha is not None:
+        L -= 0.5 * np.asarray(alpha, dtype=np.float64)[:, None]
+    return L
+
+
+def half_step_propagator(omega: np.ndarray, beta: np.ndarray, alpha: np.ndarray | None,
+                         h: float) -> np.ndarray:
+    """exp(h/2 * L(w)) per mode and frequency bin, [M, T] complex128."""
+    return np.exp(0.5 * h * linear_operator(omega, beta, alpha))
+
+
+def apply_linear(X: np.ndarray, E: np.ndarray) -> np.ndarray:
+    """Apply a frequency-domain factor E to every row: ifft(E * fft(X))."""
+    return np.fft.ifft(E * np.fft.fft(X, axis=-1), axis=-1)
+
+
+# ----------------------------------------------------------------------------
+# the Kerr term N(X)_p = i gamma sum_{l,m,n} S_plmn X_l X_m conj(X_n)
+# ----------------------------------------------------------------------------
+
+class KerrGeneric:
+    """Kerr term for any real S (no symmetry assumed).
+
+    C_pn(t) = sum_{l,m} S_plmn X_l(t) X_m(t) is one matrix product of the
+    [(p,n), (l,m)] view of S with the [(l,m), t] products; then
+    N_p(t) = i gamma sum_n C_pn(t) conj(X_n(t)).  Chunked over t only to bound
+    memory.
+    """
+
+    def __init__(self, S: np.ndarray, gamma: float, chunk: int = 4096):
+        S = np.asarray(S, dtype=np.float64)
+        M = S.shape[0]
+        if S.shape != (M, M, M, M):
+            raise ValueError("S must be [M,M,M,M]")
+        self.M = M
+        self.gamma = float(gamma)
+        self.chunk = chunk
+        # rows (p, n), columns (l, m)
+        self.Smat = np.ascontiguousarray(S.transpose(0, 3, 1, 2).reshape(M * M, M * M))
+
+    def __call__(self, X: np.ndarray) -> np.ndarray:
+        M = self.M
+        X = np.asarray(X, dtype=np.complex128)
+        T = X.shape[1]
+        out = np.empty((M, T), dtype=np.complex128)
+        for s in range(0, T, self.chunk):
+            x = X[:, s:s + self.chunk]
+            B = (x[:, None, :] * x[None, :, :]).reshape(M * M, -1)      # [(l,m), t]
+            C = (self.Smat @ B.real + 1j * (self.Smat @ B.imag)).reshape(M, M, -1)  # [p, n, t]
+            out[:, s:s + self.chunk] = 1j * self.gamma * np.einsum("pnt,nt->pt", C, np.conj(x))
+        return out
+
+
+class KerrPacked:
+    """Kerr term for S symmetric in (l,m) and in (p,n).
+
+    With q = (l <= m) and weight w_q = 2 for l < m (1 for l == m),
+    C_pn = sum_q w_q S_p,l_q,m_q,n X_l X_m, and C_pn = C_np, so only the
+    P = M(M+1)/2 rows p <= n are formed:
+    N_p = i gamma (sum_{n >= p} C_pn conj(X_n) + sum_{n < p} C_np conj(X_n)).
+    """
+
+    def __init__(self, S: np.ndarray, gamma: float, chunk: int = 4096):
+        S = np.asarray(S, dtype=np.float64)
+        M = S.shape[0]
+        a, b = np.triu_indices(M)
+        w = np.where(a < b, 2.0, 1.0)
+        # rows r = (p=a_r, n=b_r), columns q = (l=a_q, m=b_q)
+        self.Smat = np.ascontiguousarray(S[a[:, None], a[None, :], b[None, :], b[:, None]] * w[None, :])
+        self.a, self.b = a, b
+        self.off = a < b
+        self.M = M
+        self.gamma = float(gamma)
+        self.chunk = chunk
+
+    def __call__(self, X: np.ndarray) -> np.ndarray:
+        X = np.asarray(X, dtype=np.complex128)
+        a, b = self.a, self.b
+        out = np.zeros_like(X)
+        for s in range(0, X.shape[1], self.chunk):
+            x = X[:, s:s + self.chunk]
+            B = x[a] * x[b]                                            # [q, t]
+            C = self.Smat @ B.real + 1j * (self.Smat @ B.imag)          # [r, t]
+            o = np.zeros_like(x)
+            np.add.at(o, a, C * np.conj(x[b]))
+            np.add.at(o, b[self.off], C[self.off] * np.conj(x[a[self.off]]))
+            out[:, s:s + self.chunk] = 1j * self.gamma * o
+        return out
+
+
+def kerr_term(X: np.ndarray, S: np.ndarray, gamma: float) -> np.ndarray:
+    """N(X) for any S (generic form)."""
+    return KerrGeneric(S, gamma)(X)
+
+
+# ----------------------------------------------------------------------------
+# the RK4IP step, Eq. (6a-f)
+# ----------------------------------------------------------------------------
+
+def rk4ip_step(A: np.ndarray, E: np.ndarray, h: float, N) -> np.ndarray:
+    """Advance A(z) to A(z+h); E = exp(h/2 L), N = callable Kerr term."""
+    AI = apply_linear(A, E)                                   # (6a)
+    k1 = apply_linear(h * N(A), E)                            # (6b)
+    k2 = h * N(AI + k1 / 2.0)                                 # (6c)
+    k3 = h * N(AI + k2 / 2.0)                                 # (6d)
+    k4 = h * N(apply_linear(AI + k3, E))                      # (6e)
+    return apply_linear(AI + k1 / 6.0 + k2 / 3.0 + k3 / 3.0, E) + k4 / 6.0   # (6f)
+
+
+def _kerr_for(S, gamma, kerr):
+    if kerr is not None and not isinstance(kerr, str):
+        return kerr
+    S = np.asarray(S)
+    if kerr == "packed":
+        return KerrPacked(S, gamma)
+    return KerrGeneric(S, gamma)
+
+
+def propagate(A0: np.ndarray, beta: np.ndarray, alpha: np.ndarray | None, S: np.ndarray,
+              gamma: float, dt: float, h: float, n_steps: int, kerr=None,
+              callback=None) -> np.ndarray:
+    """n_steps fixed RK4IP steps of size h from A0 (promoted to complex128).
+
+    ``kerr`` may be None/"generic", "packed" (S must be symmetric in (l,m) and
+    (p,n)), or a ready callable.  ``callback(step, A)`` is called after each
+    step when given.
+    """
+    A = np.array(A0, dtype=np.complex128, copy=True)
+    M, T = A.shape
+    E = half_step_propagator(angular_frequencies(T, dt), beta, alpha, h)
+    N = _kerr_for(S, gamma, kerr)
+    for s in range(n_steps):
+        A = rk4ip_step(A, E, h, N)
+        if callback is not None:
+            callback(s + 1, A)
+    return A
+
+
+def power(A: np.ndarray, dt: float) -> float:
+    """Total power integral dt * sum_p sum_t |A_p(t)|^2 (W ps)."""
+    return float(dt * np.sum(np.abs(np.asarray(A, dtype=np.complex128)) ** 2))
+
+
+def step_doubling_estimate(A: np.ndarray, beta, alpha, S, gamma: float, dt: float, h: float,
+                           kerr=None) -> tuple[float, np.ndarray]:
+    """Richardson estimate for the local error of two h-steps from A.
+
+    delta = ||fine - coarse|| / ||fine|| with fine = two steps of h and
+    coarse = one step of 2h from the same state; for a 4th-order scheme the
+    error of ``fine`` is about delta/15.  Returns (delta, fine).
+    """
+    M, T = np.shape(A)
+    w = angular_frequencies(T, dt)
+    N = _kerr_for(S, gamma, kerr)
+    A = np.asarray(A, dtype=np.complex128)
+    Eh = half_step_propagator(w, beta, alpha, h)
+    E2h = half_step_propagator(w, beta, alpha, 2.0 * h)
+    fine = rk4ip_step(rk4ip_step(A, Eh, h, N), Eh, h, N)
+    coarse = rk4ip_step(A, E2h, 2.0 * h, N)
+    delta = float(np.linalg.norm(fine - coarse) / np.linalg.norm(fine))
+    return delta, fine

@@ -1,0 +1,351 @@
+"""Pins of the FP64 oracle to the paper and to mathematics (CPU only).
+
+None of these compares the oracle with a retyped copy of itself: each test
+checks a closed-form solution, an analytic derivative, an exact symmetry or
+a textbook special case that a plausible mistake (dropped term, wrong sign,
+wrong index, transposed operand, misplaced propagator) would violate.  The
+``mutant`` tests plant such mistakes in a copy of the oracle and show that the
+pins catch them.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import rk4ip as R
+from workloads import pair_exchange_tensor, soliton_problem, symmetric_gaussian_tensor
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _rng(k):
+    return np.random.default_rng((1901, 1895, k))
+
+
+def _crandn(rng, *shape):
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / math.sqrt(2)
+
+
+# ----------------------------------------------------------------------------
+# linear operator (Eq. 1)
+# ----------------------------------------------------------------------------
+
+def test_linear_operator_matches_analytic_gaussian_derivatives():
+    """L applied spectrally equals -a/2 g + i sum_n (i^n/n!) beta_n g^(n) with the
+    derivatives of a Gaussian written out by hand (Hermite polynomials)."""
+    T, dt, s = 1024, 0.1, 1.5
+    t = oracle.time_grid(T, dt)
+    g = np.exp(-t ** 2 / (2 * s ** 2))
+    d1 = -t / s ** 2 * g
+    d2 = (t ** 2 / s ** 4 - 1 / s ** 2) * g
+    d3 = (-t ** 3 / s ** 6 + 3 * t / s ** 4) * g
+    beta = np.array([[0.7, -3.0, 5.0, 11.0]])
+    alpha = np.array([0.46])
+    expect = -alpha[0] / 2 * g + 1j * (beta[0, 0] * g + 1j * beta[0, 1] * d1
+                                      - beta[0, 2] / 2 * d2 - 1j * beta[0, 3] / 6 * d3)
+    L = oracle.linear_operator(oracle.angular_frequencies(T, dt), beta, alpha)
+    got = np.fft.ifft(L[0] * np.fft.fft(g))
+    assert _rel(got, expect) < 1e-11
+
+
+def test_beta1_shift_is_circular_roll():
+    """beta1 * L = k dt delays the field by exactly k samples (group delay sign)."""
+    rng = _rng(1)
+    T, dt, k = 512, 0.25, 7
+    A0 = _crandn(rng, 2, T)
+    h, n = 0.1, 10
+    beta = np.array([[0.0, k * dt / (h * n), 0.0], [0.0, -k * dt / (h * n), 0.0]])
+    out = oracle.propagate(A0, beta, None, np.zeros((2, 2, 2, 2)), 1.0, dt, h, n)
+    assert _rel(out[0], np.roll(A0[0], k)) < 1e-13
+    assert _rel(out[1], np.roll(A0[1], -k)) < 1e-13
+
+
+def test_beta2_gaussian_broadening_closed_form():
+    """Linear GVD of a Gaussian: T0/sqrt(T0^2 - i b2 z) exp(-t^2/(2(T0^2 - i b2 z)))."""
+    T, dt, T0, b2, z = 8192, 0.05, 3.0, -20.0, 0.7
+    t = oracle.time_grid(T, dt)
+    A0 = np.exp(-t ** 2 / (2 * T0 ** 2))[None, :]
+    out = oracle.propagate(A0, np.array([[0.0, 0.0, b2]]), None, np.zeros((1, 1, 1, 1)), 0.0,
+                           dt, z / 35, 35)
+    c = T0 ** 2 - 1j * b2 * z
+    expect = T0 / np.sqrt(c) * np.exp(-t ** 2 / (2 * c))
+    assert _rel(out[0], expect) < 1e-12
+
+
+def test_attenuation_and_beta0():
+    rng = _rng(2)
+    A0 = _crandn(rng, 1, 64)
+    out = oracle.propagate(A0, np.array([[3.0]]), np.array([0.2]), np.zeros((1, 1, 1, 1)), 0.0,
+                           1.0, 0.5, 4)
+    assert _rel(out, A0 * np.exp(-0.1 * 2.0 + 3j * 2.0)) < 1e-14
+
+
+# ----------------------------------------------------------------------------
+# Kerr term wiring
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("idx", [(0, 1, 2, 3), (3, 0, 1, 2), (2, 2, 1, 0), (1, 3, 3, 1), (0, 0, 0, 0)])
+def test_kerr_single_entry_tensor(idx):
+    """S with one unit entry at (p,l,m,n): only output p is nonzero and equals
+    i gamma X_l X_m conj(X_n) (p is the output index, n the conjugated one)."""
+    rng = _rng(3)
+    M, g = 4, 0.8
+    X = _crandn(rng, M, 16)
+    S = np.zeros((M,) * 4)
+    S[idx] = 1.0
+    got = oracle.kerr_term(X, S, g)
+    p, l, m, n = idx
+    expect = np.zeros_like(X)
+    expect[p] = 1j * g * X[l] * X[m] * np.conj(X[n])
+    assert np.max(np.abs(got - expect)) < 1e-14
+
+
+def test_kerr_linear_in_S():
+    rng = _rng(4)
+    M = 3
+    X = _crandn(rng, M, 8)
+    S1, S2 = rng.standard_normal((M,) * 4), rng.standard_normal((M,) * 4)
+    lhs = oracle.kerr_term(X, S1 + 2.5 * S2, 1.0)
+    rhs = oracle.kerr_term(X, S1, 1.0) + 2.5 * oracle.kerr_term(X, S2, 1.0)
+    assert _rel(lhs, rhs) < 1e-13
+
+
+def _dPdz(X, N):
+    return 2.0 * np.real(np.sum(np.conj(X) * N))
+
+
+def test_kerr_conserves_power_exactly_for_pair_exchange_symmetry():
+    """Re sum_p conj(X_p) N_p = 0 iff sum S_plmn conj(X_p X_n) X_l X_m is real, which
+    holds exactly when S_plmn = S_lpnm; a generic S does not conserve power."""
+    rng = _rng(5)
+    M = 5
+    X = _crandn(rng, M, 32)
+    S = pair_exchange_tensor(M, rng)
+    N = oracle.kerr_term(X, S, 1.0)
+    scale = np.sum(np.abs(N) * np.abs(X))
+    assert abs(_dPdz(X, N)) < 1e-13 * scale
+    G = rng.standard_normal((M,) * 4)
+    NG = oracle.kerr_term(X, G, 1.0)
+    assert abs(_dPdz(X, NG)) > 1e-6 * np.sum(np.abs(NG) * np.abs(X))
+
+
+def test_packed_equals_generic_for_symmetric_tensor():
+    for M in (1, 2, 5, 9):
+        rng = _rng(10 + M)
+        S = symmetric_gaussian_tensor(M, rng)
+        X = _crandn(rng, M, 100)
+        a = oracle.KerrPacked(S, 0.7, chunk=37)(X)
+        b = oracle.KerrGeneric(S, 0.7, chunk=41)(X)
+        assert _rel(a, b) < 1e-13
+
+
+def test_packed_needs_only_lm_and_pn_symmetry():
+    """Packed form is exact for S symmetric in (l,m) and (p,n) but not fully symmetric."""
+    rng = _rng(6)
+    M = 4
+    G = rng.standard_normal((M,) * 4)
+    S = G + G.transpose(0, 2, 1, 3)
+    S = S + S.transpose(3, 1, 2, 0)
+    X = _crandn(rng, M, 50)
+    assert _rel(oracle.KerrPacked(S, 1.0)(X), oracle.KerrGeneric(S, 1.0)(X)) < 1e-13
+
+
+# ----------------------------------------------------------------------------
+# closed-form nonlinear solutions
+# ----------------------------------------------------------------------------
+
+def test_rank_one_tensor_closed_form():
+    """S = u x u x u x u, no dispersion: s = u.A obeys ds/dz = i g |u|^2 |s|^2 s, so
+    s(z) = s0 exp(i g |u|^2 |s0|^2 z) and A_p(z) = A_p(0) + u_p (s(z) - s0)/|u|^2."""
+    rng = _rng(7)
+    M, T = 4, 64
+    u = rng.standard_normal(M)
+    S = np.einsum("a,b,c,d->abcd", u, u, u, u)
+    A0 = 0.25 * _crandn(rng, M, T)
+    g, z = 1.1, 0.5
+    uu = u @ u
+    s0 = u @ A0
+    sz = s0 * np.exp(1j * g * uu * np.abs(s0) ** 2 * z)
+    expect = A0 + u[:, None] * (sz - s0)[None, :] / uu
+    errs = []
+    for n in (50, 100):
+        out = oracle.propagate(A0, np.zeros((M, 1)), None, S, g, 1.0, z / n, n)
+        errs.append(_rel(out, expect))
+    assert errs[-1] < 1e-8
+    assert 13.0 < errs[0] / errs[1] < 17.5
+
+
+def test_spm_phase_rotation_and_fourth_order():
+    """One mode, no dispersion: A(z) = A0 exp(i g |A0|^2 z); RK4 error drops 16x per halving."""
+    p = soliton_problem(T=256, noise=0.0)
+    A0 = p.A0
+    z = 0.4
+    exact = A0 * np.exp(1j * p.gamma * np.abs(A0) ** 2 * z)
+    errs = []
+    for n in (16, 32, 64):
+        out = oracle.propagate(A0, np.zeros((1, 1)), None, p.S, p.gamma, p.dt, z / n, n)
+        errs.append(_rel(out, exact))
+    assert errs[-1] < 2e-7
+    for e1, e2 in zip(errs, errs[1:]):
+        assert 13.0 < e1 / e2 < 17.5
+
+
+def test_cw_with_beta0_rotates_exactly_in_interaction_picture():
+    """CW input, large beta0 and SPM: A(z) = sqrt(P) exp(i (beta0 + g P) z).  The
+    interaction picture handles beta0 exactly, leaving only the RK4 error of SPM;
+    a missing or misplaced half-step propagator gives an O(beta0 h) error."""
+    P, g, b0 = 2.0, 1.3, 400.0
+    A0 = np.full((1, 32), math.sqrt(P), dtype=np.complex128)
+    z, n = 1.0, 200
+    errs = []
+    for b in (b0, 0.0):
+        out = oracle.propagate(A0, np.array([[b, 0.0, -20.0]]), None, np.ones((1, 1, 1, 1)), g,
+                               0.5, z / n, n)
+        exact = math.sqrt(P) * np.exp(1j * (b + g * P) * z)
+        errs.append(np.max(np.abs(out[0] - exact)) / math.sqrt(P))
+    # the only error left is RK4 on the SPM phase, identical with and without beta0
+    assert errs[0] < 1e-8
+    assert abs(errs[0] - errs[1]) < 1e-12
+
+
+def test_reduces_to_classical_rk4_without_linear_part():
+    """E == 1: one RK4IP step is the textbook RK4 step y + h/6 (f1 + 2 f2 + 2 f3 + f4)."""
+    rng = _rng(8)
+    M = 3
+    S = symmetric_gaussian_tensor(M, rng)
+    N = oracle.KerrGeneric(S, 2.0)
+    y = _crandn(rng, M, 40)
+    h = 0.03
+    f1 = N(y)
+    f2 = N(y + h / 2 * f1)
+    f3 = N(y + h / 2 * f2)
+    f4 = N(y + h * f3)
+    textbook = y + h / 6 * (f1 + 2 * f2 + 2 * f3 + f4)
+    got = oracle.rk4ip_step(y, np.ones((M, 40)), h, N)
+    assert _rel(got, textbook) < 1e-14
+
+
+def _soliton_error(h, n):
+    p = soliton_problem(noise=0.0, h=h, n_steps=n)
+    out = oracle.propagate(p.A0, p.beta, None, p.S, p.gamma, p.dt, p.h, p.n_steps)
+    z = p.h * p.n_steps
+    t = oracle.time_grid(p.T, p.dt)
+    P0, T0 = p.meta["P0"], p.meta["T0"]
+    exact = math.sqrt(P0) / np.cosh(t / T0) * np.exp(0.5j * p.gamma * P0 * z)
+    return _rel(out[0], exact), out, p
+
+
+def test_fundamental_soliton_and_fourth_order_convergence():
+    """sqrt(P0) sech(t/T0) exp(i g P0 z / 2) with P0 = |b2|/(g T0^2) propagates unchanged;
+    the global error of RK4IP falls about 16x per step halving (4th order)."""
+    e20, _, _ = _soliton_error(0.02, 50)
+    e10, _, _ = _soliton_error(0.01, 100)
+    e5, out, p = _soliton_error(0.005, 200)
+    assert e5 < 1e-6
+    assert 13.0 < e20 / e10 < 17.5
+    assert 13.0 < e10 / e5 < 17.5
+    # power is conserved to O(h^5) for alpha = 0 and a symmetric tensor
+    assert abs(oracle.power(out, p.dt) / oracle.power(p.A0, p.dt) - 1) < 1e-8
+
+
+def test_power_conservation_multimode_scheme():
+    """alpha = 0, fully symmetric S, dispersion on: the exact flow conserves total power,
+    so the drift of the scheme is pure truncation error and falls at least 16x per
+    step halving (4th order or better)."""
+    rng = _rng(9)
+    M, T, dt = 3, 256, 0.5
+    S = symmetric_gaussian_tensor(M, rng)
+    beta = np.column_stack([rng.uniform(-5, 5, M), rng.uniform(-2, 2, M), rng.uniform(-3, -1, M)])
+    t = oracle.time_grid(T, dt)
+    A0 = np.exp(-t ** 2 / 200.0)[None, :] * (1.0 + 0.5 * rng.standard_normal((M, 1)))
+    A0 = A0.astype(np.complex128)
+    drifts = []
+    for n in (40, 80):
+        out = oracle.propagate(A0, beta, None, S, 1.0, dt, 1.0 / n, n)
+        drifts.append(abs(oracle.power(out, dt) / oracle.power(A0, dt) - 1))
+    assert drifts[1] < 1e-7
+    assert drifts[0] / max(drifts[1], 1e-300) > 14.0
+
+
+def test_step_doubling_estimate_tracks_true_error():
+    """delta/15 from one 2h step vs two h steps estimates the two-step error (Richardson)."""
+    p = soliton_problem(noise=0.0)
+    t = oracle.time_grid(p.T, p.dt)
+    P0, T0 = p.meta["P0"], p.meta["T0"]
+    h = 0.04
+    delta, fine = oracle.step_doubling_estimate(p.A0, p.beta, None, p.S, p.gamma, p.dt, h)
+    exact = math.sqrt(P0) / np.cosh(t / T0) * np.exp(0.5j * p.gamma * P0 * 2 * h)
+    true = _rel(fine[0], exact)
+    assert 0.5 < (delta / 15.0) / true < 2.0
+
+
+# ----------------------------------------------------------------------------
+# mutants: plausible mistakes planted in a copy of the oracle must fail a pin
+# ----------------------------------------------------------------------------
+
+def _step_k1_undispersed(A, E, h, N):
+    AI = R.apply_linear(A, E)
+    k1 = h * N(A)                                   # mistake: propagator dropped
+    k2 = h * N(AI + k1 / 2)
+    k3 = h * N(AI + k2 / 2)
+    k4 = h * N(R.apply_linear(AI + k3, E))
+    return R.apply_linear(AI + k1 / 6 + k2 / 3 + k3 / 3, E) + k4 / 6
+
+
+def _step_wrong_k3(A, E, h, N):
+    AI = R.apply_linear(A, E)
+    k1 = R.apply_linear(h * N(A), E)
+    k2 = h * N(AI + k1 / 2)
+    k3 = h * N(AI + k1 / 2)                         # mistake: k1 instead of k2
+    k4 = h * N(R.apply_linear(AI + k3, E))
+    return R.apply_linear(AI + k1 / 6 + k2 / 3 + k3 / 3, E) + k4 / 6
+
+
+def test_mutant_undispersed_k1_fails_cw_pin(monkeypatch):
+    monkeypatch.setattr(R, "rk4ip_step", _step_k1_undispersed)
+    P, g, b0 = 2.0, 1.3, 400.0
+    A0 = np.full((1, 32), math.sqrt(P), dtype=np.complex128)
+    out = R.propagate(A0, np.array([[b0]]), None, np.ones((1, 1, 1, 1)), g, 0.5, 1.0 / 200, 200)
+    exact = math.sqrt(P) * np.exp(1j * (b0 + g * P))
+    assert np.max(np.abs(out[0] - exact)) / math.sqrt(P) > 1e-3
+
+
+def test_mutant_wrong_stage_fails_order_pin(monkeypatch):
+    monkeypatch.setattr(R, "rk4ip_step", _step_wrong_k3)
+    e10, _, _ = _soliton_error(0.01, 100)
+    e5, _, _ = _soliton_error(0.005, 200)
+    assert not (13.0 < e10 / e5 < 17.5)
+
+
+def test_mutant_conjugated_wrong_index_fails_power_pin():
+    rng = _rng(5)
+    M = 5
+    X = _crandn(rng, M, 32)
+    S = pair_exchange_tensor(M, rng)
+    # mistake: conjugate X_l instead of X_n
+    N = 1j * np.einsum("plmn,lt,mt,nt->pt", S, np.conj(X), X, X)
+    assert abs(_dPdz(X, N)) > 1e-6 * np.sum(np.abs(N) * np.abs(X))
+
+
+def test_mutant_transposed_tensor_fails_single_entry_pin():
+    rng = _rng(3)
+    M = 4
+    X = _crandn(rng, M, 16)
+    S = np.zeros((M,) * 4)
+    S[0, 1, 2, 3] = 1.0
+    got = oracle.kerr_term(X, S.transpose(3, 1, 2, 0), 1.0)  # mistake: p and n swapped
+    assert np.max(np.abs(got[0] - 1j * X[1] * X[2] * np.conj(X[3]))) > 1e-3
+
+
+def test_mutant_beta1_sign_fails_roll_pin():
+    rng = _rng(1)
+    T, dt, k = 512, 0.25, 7
+    A0 = _crandn(rng, 1, T)
+    w = oracle.angular_frequencies(T, dt)
+    L = 1j * (k * dt) * w       # mistake: +i beta1 w instead of -i beta1 w
+    out = np.fft.ifft(np.exp(L) * np.fft.fft(A0[0]))
+    assert _rel(out, np.roll(A0[0], k)) > 0.1
