@@ -1,0 +1,172 @@
+"""Throughput of the RK4IP step on one MI355X, with roofline and CPU baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload wdm36]
+                    [--precision fp32|split_bf16] [--no-cpu-baseline]
+
+A step is one RK4IP step (Eq. 6a-f of the paper: four half-step propagators,
+four Kerr evaluations, the stage combinations) over the whole field.  The
+field and all tables are resident in HBM before the timed region; the timed
+region is K calls' worth of device work launched by mmnlse_advance,
+bracketed by synchronisation.  Prints one JSON line.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "RK4IP mode·sample·steps/s + roofline %, plain vs split-BF16; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+BF16_PEAK_TFLOPS = 2500.0
+
+WORKLOADS = {
+    "wdm36": "wdm36: M=36 modes, T=2^16 complex64, 8-ch WDM 16-QAM 32 GBd, masked symmetric S, h=50 m",
+    "qpsk6": "qpsk6: M=6 modes, T=2^14 complex64, QPSK 32 GBd, dense symmetric S, h=100 m",
+    "soliton": "soliton: M=1, T=4096, fundamental sech soliton, h=5 m",
+    "wdm120": "wdm120: M=120 modes, T=2^17 complex64, 4-ch WDM QPSK, dense symmetric S, h=20 m",
+}
+
+
+def kerr_flops_per_eval(M: int, T: int) -> float:
+    """Algorithmic flops of one Kerr evaluation h N(X) in the packed form:
+    B_q = X_l X_m (6 flops per pair and sample), C = S_pack B (real P x P
+    times complex P x T: 4 P^2 T), out_p = sum_n C_pn conj(X_n) (8 per (p,n)
+    term, M^2 terms per sample)."""
+    P = M * (M + 1) // 2
+    return 4.0 * P * P * T + 6.0 * P * T + 8.0 * M * M * T
+
+
+def linear_bytes_per_apply(M: int, T: int, four_step: bool) -> float:
+    """Algorithmic HBM bytes of one half-step propagator application on one
+    field: read + write of M*T complex64 plus the M*T hi+lo factor table
+    (16 B per entry).  A four-step transform needs two more read + write
+    passes (the strided column passes)."""
+    passes = 3 if four_step else 1
+    return M * T * (16.0 * passes + 16.0)
+
+
+def cpu_baseline(p, seconds_target: float = 15.0):
+    """Time the FP64 oracle on this host over a bounded number of steps."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    kern = oracle.KerrPacked(p.S, p.gamma) if p.symmetric else oracle.KerrGeneric(p.S, p.gamma)
+    E = oracle.half_step_propagator(oracle.angular_frequencies(p.T, p.dt), p.beta, None, p.h)
+    A = p.A0.astype(np.complex128)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        A = oracle.rk4ip_step(A, E, p.h, kern)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > seconds_target or steps >= p.n_steps:
+            break
+    v = p.M * p.T * steps / el
+    return {"value": v, "unit": "mode*sample*steps/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{steps} RK4IP steps of the full {p.name} field (M={p.M}, T={p.T}), FP64 numpy, "
+                      f"{el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="wdm36", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the RK4IP path here is single-device (fields and the "
+              "coupling tensor fit one MI355X); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1901_01895_amd as mm
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    mm.load()
+    p = W.make_problem(args.workload)
+    prec = mm.FP32 if args.precision == "fp32" else mm.SPLIT_BF16
+    P = mm.Propagator.from_problem(p, precision=prec)
+    A0 = torch.from_numpy(p.A0.astype(np.complex64)).cuda()
+    A = A0.clone()
+
+    # warmup
+    P.advance(A, args.warmup)
+    torch.cuda.synchronize()
+    # timed region
+    A.copy_(A0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.advance(A, args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = 1e3 * el / args.steps
+    value = p.M * p.T * args.steps / el
+
+    # per-kernel device time (HIP events on the plan's stream), same step count
+    B = A0.clone()
+    prof = P.profile(B, args.steps)
+    four = p.T > 16384
+    kerr_avg_ms = prof["kerr_ms"] / max(prof["kerr_launches"], 1)
+    lin_avg_ms = prof["linear_ms"] / max(prof["linear_launches"], 1)
+    kflops = kerr_flops_per_eval(p.M, p.T)
+    evals_per_launch = prof["kerr_evals"] / max(prof["kerr_launches"], 1)
+    kerr_tflops = kflops * evals_per_launch / (kerr_avg_ms * 1e-3) / 1e12
+    lin_gbs = 2 * linear_bytes_per_apply(p.M, p.T, four) / (lin_avg_ms * 1e-3) / 1e9
+    kerr_dominant = prof["kerr_ms"] >= prof["linear_ms"]
+    path = P.kerr_path
+    if kerr_dominant:
+        if path == "mfma" and prec == mm.SPLIT_BF16:
+            bound, peak = "mfma", BF16_PEAK_TFLOPS
+        elif path == "mfma":
+            bound, peak = "mfma", FP32_PEAK_TFLOPS
+        else:
+            bound, peak = "alu", FP32_PEAK_TFLOPS
+        roof = {"bound": bound, "achieved": kerr_tflops, "peak": peak, "unit": "TFLOP/s",
+                "frac": kerr_tflops / peak, "traffic": None, "kernel": f"kerr_{path}",
+                "avg_launch_ms": kerr_avg_ms}
+    else:
+        roof = {"bound": "hbm", "achieved": lin_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": lin_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "linear_half_step",
+                "avg_launch_ms": lin_avg_ms}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "mode*sample*steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == mm.FP32 else "bf16x3-split/f32-acc", "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "M": p.M, "T": p.T, "h_km": p.h,
+                   "precision": args.precision, "kerr_kernel": path},
+        "roofline": roof,
+        "kernels": {"kerr_ms_per_step": prof["kerr_ms"] / args.steps,
+                    "linear_ms_per_step": prof["linear_ms"] / args.steps,
+                    "kerr_tflops": kerr_tflops, "linear_GBps": lin_gbs},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    P.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * mmnlse.h -- RK4IP propagation of coupled multimode nonlinear Schroedinger
+ * equations on one AMD Instinct MI355X (gfx950).
+ *
+ * The library advances a field A[M][T] (M modes, T time samples per mode)
+ * along a fiber with the fourth-order Runge-Kutta method in the interaction
+ * picture, Eq. (6a-f) of Brehler, Schirwon, Krummrich, Goeddeke,
+ * "Simulation of Nonlinear Signal Propagation in Multimode Fibers on
+ * Multi-GPU Systems" (Section 3.2), with:
+ *
+ *   linear part (Eq. 1, operator L): -alpha_p/2 + i sum_n beta_{n,p} (-w)^n / n!
+ *       applied per mode in the frequency domain (Section 3.1);
+ *   Kerr part: N_p = i gamma sum_{l,m,n} S_plmn A_l A_m conj(A_n), the
+ *       general multimode form the paper cites in Section 2 (for M = 1 it is
+ *       the paper's gamma |A|^2 A).
+ *
+ * Conventions
+ *   - Units: t in ps, z in km, power in W, beta_n in ps^n/km, gamma in 1/(W km).
+ *   - Fields are complex, interleaved (re, im), row-major [M][T]: each mode's
+ *     T samples are contiguous (the paper's row-major signal matrix,
+ *     Section 4).  T must be a power of two, 64 <= T <= 2^20.
+ *   - Forward transform kernel exp(-i w t); w = 2 pi fftfreq(T, dt) with the
+ *     Nyquist bin negative.
+ *   - Eq. (6b) is read as k1 = exp(h/2 L)[h N(A(z))].
+ *   - Device pointers must belong to the handle's device and are used in
+ *     stream order on the handle's stream.  The caller owns every pointer it
+ *     passes; nothing is retained after a call returns.
+ *   - Every function returns an mmnlse_status and never throws.  On error
+ *     mmnlse_last_error() describes the failure (thread-local string, valid
+ *     until the next call on the same thread).  A failed call leaves the
+ *     handle usable, except after MMNLSE_E_DEVICE.
+ *   - One handle must not be used from two host threads at once.
+ */
+#ifndef MMNLSE_H
+#define MMNLSE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MMNLSE_OK = 0,
+  MMNLSE_E_INVALID = 1,     /* bad argument or configuration */
+  MMNLSE_E_NOMEM = 2,       /* device or host allocation failed, or budget exceeded */
+  MMNLSE_E_DEVICE = 3,      /* HIP runtime error */
+  MMNLSE_E_NONFINITE = 4,   /* NaN or Inf found in an input or result */
+  MMNLSE_E_BUSY = 5,        /* request not finished yet (serving) */
+  MMNLSE_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+} mmnlse_status;
+
+/* Arithmetic of the Kerr contraction; FFTs and field storage are FP32 in both. */
+typedef enum {
+  MMNLSE_FP32 = 0,        /* FP32 products, FP32 accumulation */
+  MMNLSE_SPLIT_BF16 = 1   /* S and A_l A_m split into bf16 hi + lo; hi*hi + hi*lo + lo*hi
+                             on matrix cores with FP32 accumulation (needs a symmetric S) */
+} mmnlse_precision;
+
+typedef enum { MMNLSE_C64 = 0, MMNLSE_C128 = 1 } mmnlse_dtype;
+
+/* S is symmetric in (l,m) and in (p,n): S_plmn == S_pmln == S_nlmp (checked to
+ * 1e-6 relative at create).  Enables the packed contraction over the
+ * P = M(M+1)/2 pairs.  Every tensor symmetric under all index permutations
+ * qualifies. */
+#define MMNLSE_S_SYMMETRIC 0x1u
+/* Force the unpacked per-sample Kerr kernel (any S). */
+#define MMNLSE_KERR_GENERIC 0x2u
+
+typedef struct {
+  int32_t M;             /* modes (rows), 1 <= M <= 256 */
+  int32_t T;             /* samples per mode, power of two, 64 <= T <= 2^20 */
+  double dt_ps;          /* sample spacing in ps, > 0 */
+  int32_t n_beta;        /* number of Taylor coefficients beta_0..beta_{n_beta-1}, 0..8 */
+  const double *beta;    /* [M][n_beta] host array, ps^n/km; copied at create */
+  const double *alpha;   /* [M] host array, power attenuation in 1/km, or NULL for 0 */
+  const float *S;        /* [M][M][M][M] host array, index order (p,l,m,n); copied */
+  double gamma;          /* nonlinear coefficient, 1/(W km) */
+  double h_km;           /* step size, > 0 */
+  double L_km;           /* fiber length; L/h must be an integer within 1e-9 relative */
+  int32_t precision;     /* mmnlse_precision */
+  uint32_t flags;        /* MMNLSE_S_SYMMETRIC | MMNLSE_KERR_GENERIC */
+} mmnlse_config;
+
+typedef struct {
+  double power_in;       /* dt * sum |A_in|^2 in W ps, FP64 reduction on the device */
+  double power_out;      /* same for the result */
+  double seconds;        /* wall time of the step loop (host clock, synchronised) */
+  int64_t steps;         /* RK4IP steps taken */
+} mmnlse_stats;
+
+typedef struct mmnlse_ctx *mmnlse_t;
+
+/* Create a propagation plan on the current HIP device.
+ * Copies beta, alpha and S to the device, tabulates exp(h/2 L) per mode and
+ * bin in FP64 (stored as FP32 hi + lo), the FFT twiddles likewise, and the
+ * Kerr tensor in the layout of the selected kernel.  Allocates three field
+ * buffers of M*T complex64 as workspace.  `stream` is a hipStream_t (NULL =
+ * the default stream); the handle does not own it.
+ * Errors: E_INVALID (sizes, L/h, symmetry flag not satisfied, split precision
+ * without MMNLSE_S_SYMMETRIC), E_NOMEM, E_DEVICE. */
+mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *out);
+
+/* Release everything create allocated.  NULL is accepted. */
+mmnlse_status mmnlse_destroy(mmnlse_t h);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *mmnlse_last_error(void);
+
+/* Propagate over the configured length, L/h RK4IP steps (Eq. 6a-f).
+ * A_in, A_out: [M][T] complex of type `dtype` (mmnlse_dtype); host pointers
+ * when on_device == 0 (the call then copies, runs and synchronises), device
+ * pointers when on_device != 0 (still synchronises before returning, so
+ * that `st` is filled).  A_out may equal A_in.  complex128 data is rounded
+ * to complex64 on the device before the first step.  `st` may be NULL.
+ * Errors: E_INVALID, E_NONFINITE (non-finite input or result power),
+ * E_DEVICE. */
+mmnlse_status mmnlse_propagate(mmnlse_t h, const void *A_in, void *A_out, int32_t dtype,
+                               int32_t on_device, mmnlse_stats *st);
+
+/* Advance a device-resident complex64 field A[M][T] in place by n_steps
+ * RK4IP steps of size h (n_steps >= 0), asynchronously on the handle's
+ * stream.  This is the hot path with no host transfer and no host sync.
+ * Errors: E_INVALID, E_DEVICE (launch failure). */
+mmnlse_status mmnlse_advance(mmnlse_t h, void *A, int64_t n_steps);
+
+/* One application of the half-step linear propagator exp(h/2 L) (the
+ * operator of Eq. 6a) to every row: Y = IFFT(exp(h/2 L) * FFT(X)).
+ * X, Y: device complex64 [M][T]; Y may equal X.  Asynchronous. */
+mmnlse_status mmnlse_linear_half_step(mmnlse_t h, const void *X, void *Y);
+
+/* The Kerr increment Y = h * N(X), N_p = i gamma sum S_plmn X_l X_m conj(X_n)
+ * (the bracketed terms of Eq. 6b-e), with the handle's tensor and precision.
+ * X, Y: device complex64 [M][T]; Y must not overlap X.  Asynchronous. */
+mmnlse_status mmnlse_kerr(mmnlse_t h, const void *X, void *Y);
+
+/* FP64 reduction of dt * sum_p sum_t |X_p(t)|^2 for a device complex64
+ * field; synchronises and writes *out (host).  Total power is conserved by
+ * Eq. (1) for alpha = 0 and a tensor with S_plmn == S_lpnm. */
+mmnlse_status mmnlse_power(mmnlse_t h, const void *X, double *out);
+
+/* Step-doubling local error estimate (Richardson): from device field X,
+ * takes two RK4IP steps of h and one step of 2h, and writes
+ * delta = ||fine - coarse|| / ||fine|| computed in FP64 to *delta (host).
+ * The error of the fine result is about delta/15 (fourth order, Section
+ * 3.2).  X is not modified.  Synchronises. */
+mmnlse_status mmnlse_step_doubling(mmnlse_t h, const void *X, double *delta);
+
+/* Measurement: run n_steps exactly like mmnlse_advance, with a HIP event
+ * pair recorded on the handle's stream around every kernel-class launch,
+ * synchronise, and report the summed device time per class in
+ * ms[0] (Kerr launches) and ms[1] (linear half-step applications; a
+ * four-step transform is three kernels timed as one application), with the
+ * launch counts in counts[0], counts[1] and the number of Kerr evaluations
+ * h N(.) in counts[2].  A is advanced in place.  Errors: E_INVALID,
+ * E_DEVICE. */
+mmnlse_status mmnlse_profile(mmnlse_t h, void *A, int64_t n_steps, double *ms, int64_t *counts);
+
+/* Wait for all work queued on the handle's stream. */
+mmnlse_status mmnlse_synchronize(mmnlse_t h);
+
+/* Bytes of device memory the handle holds (workspace, tables, tensor). */
+mmnlse_status mmnlse_footprint(const mmnlse_t h, size_t *bytes);
+
+/* Kernel used for the Kerr term: 0 = per-sample register kernel (M <= 8),
+ * 1 = generic LDS kernel (any S), 2 = packed matrix-core contraction. */
+mmnlse_status mmnlse_kerr_path(const mmnlse_t h, int32_t *path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MMNLSE_H */

@@ -127,7 +127,8 @@ class KerrGeneric:
         for s in range(0, T, self.chunk):
             x = X[:, s:s + self.chunk]
             B = (x[:, None, :] * x[None, :, :]).reshape(M * M, -1)      # [(l,m), t]
-            C = (self.Smat @ B.real + 1j * (self.Smat @ B.imag)).reshape(M, M, -1)  # [p, n, t]
+            Br, Bi = np.ascontiguousarray(B.real), np.ascontiguousarray(B.imag)
+            C = (self.Smat @ Br + 1j * (self.Smat @ Bi)).reshape(M, M, -1)  # [p, n, t]
             out[:, s:s + self.chunk] = 1j * self.gamma * np.einsum("pnt,nt->pt", C, np.conj(x))
         return out
 
@@ -161,7 +162,8 @@ class KerrPacked:
         for s in range(0, X.shape[1], self.chunk):
             x = X[:, s:s + self.chunk]
             B = x[a] * x[b]                                            # [q, t]
-            C = self.Smat @ B.real + 1j * (self.Smat @ B.imag)          # [r, t]
+            Br, Bi = np.ascontiguousarray(B.real), np.ascontiguousarray(B.imag)
+            C = self.Smat @ Br + 1j * (self.Smat @ Bi)                  # [r, t]
             o = np.zeros_like(x)
             np.add.at(o, a, C * np.conj(x[b]))
             np.add.at(o, b[self.off], C[self.off] * np.conj(x[a[self.off]]))

@@ -1,0 +1,238 @@
+"""Python binding of libmmnlse (ctypes), RK4IP for coupled multimode NLSEs on MI355X.
+
+Argument marshalling only: every step of the propagation runs in the HIP
+library.  PyTorch supplies device memory and the stream.  The library must
+have been built (``python -m paper_1901_01895_amd.build``); loading fails
+loudly otherwise, there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmmnlse.so")
+
+FP32, SPLIT_BF16 = 0, 1
+C64, C128 = 0, 1
+S_SYMMETRIC, KERR_GENERIC = 0x1, 0x2
+KERR_PATHS = {0: "small", 1: "tiled", 2: "mfma"}
+
+STATUS = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NONFINITE", 5: "E_BUSY",
+          6: "E_UNSUPPORTED"}
+
+SYMBOLS = (
+    "mmnlse_create", "mmnlse_destroy", "mmnlse_last_error", "mmnlse_propagate", "mmnlse_advance",
+    "mmnlse_linear_half_step", "mmnlse_kerr", "mmnlse_power", "mmnlse_step_doubling",
+    "mmnlse_synchronize", "mmnlse_footprint", "mmnlse_kerr_path", "mmnlse_profile",
+)
+
+
+class MMNLSEError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("M", ctypes.c_int32), ("T", ctypes.c_int32), ("dt_ps", ctypes.c_double),
+        ("n_beta", ctypes.c_int32), ("beta", ctypes.POINTER(ctypes.c_double)),
+        ("alpha", ctypes.POINTER(ctypes.c_double)), ("S", ctypes.POINTER(ctypes.c_float)),
+        ("gamma", ctypes.c_double), ("h_km", ctypes.c_double), ("L_km", ctypes.c_double),
+        ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("power_in", ctypes.c_double), ("power_out", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("steps", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_1901_01895_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    lib.mmnlse_create.argtypes = [ctypes.POINTER(Config), vp, ctypes.POINTER(vp)]
+    lib.mmnlse_destroy.argtypes = [vp]
+    lib.mmnlse_last_error.restype = ctypes.c_char_p
+    lib.mmnlse_last_error.argtypes = []
+    lib.mmnlse_propagate.argtypes = [vp, vp, vp, i32, i32, ctypes.POINTER(Stats)]
+    lib.mmnlse_advance.argtypes = [vp, vp, i64]
+    lib.mmnlse_linear_half_step.argtypes = [vp, vp, vp]
+    lib.mmnlse_kerr.argtypes = [vp, vp, vp]
+    lib.mmnlse_power.argtypes = [vp, vp, dp]
+    lib.mmnlse_step_doubling.argtypes = [vp, vp, dp]
+    lib.mmnlse_synchronize.argtypes = [vp]
+    lib.mmnlse_footprint.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+    lib.mmnlse_kerr_path.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.mmnlse_profile.argtypes = [vp, vp, i64, dp, ctypes.POINTER(ctypes.c_int64)]
+    for name in SYMBOLS:
+        if name != "mmnlse_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise MMNLSEError(status, load().mmnlse_last_error().decode())
+
+
+def _dptr(x) -> int:
+    """Device pointer of a contiguous complex64 CUDA tensor."""
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex64 and x.is_contiguous()):
+        raise TypeError("expected a contiguous complex64 device tensor")
+    return x.data_ptr()
+
+
+class Propagator:
+    """One RK4IP plan: fixed M, T, coefficients, tensor, h and L.
+
+    Parameters mirror ``mmnlse_config``; ``stream`` is a torch.cuda.Stream
+    (default: torch's current stream).
+    """
+
+    def __init__(self, M: int, T: int, dt: float, beta, S, gamma: float, h: float, L: float,
+                 alpha=None, precision: int = FP32, symmetric: bool | None = None,
+                 generic: bool = False, stream=None):
+        import torch
+        lib = load()
+        self._beta = np.ascontiguousarray(np.asarray(beta, dtype=np.float64).reshape(M, -1))
+        self._S = np.ascontiguousarray(np.asarray(S, dtype=np.float32).reshape(M, M, M, M))
+        self._alpha = None if alpha is None else np.ascontiguousarray(np.asarray(alpha, dtype=np.float64))
+        if symmetric is None:
+            s = self._S
+            symmetric = bool(np.array_equal(s, s.transpose(0, 2, 1, 3)) and np.array_equal(s, s.transpose(3, 1, 2, 0)))
+        flags = (S_SYMMETRIC if symmetric else 0) | (KERR_GENERIC if generic else 0)
+        cfg = Config()
+        cfg.M, cfg.T, cfg.dt_ps = M, T, float(dt)
+        cfg.n_beta = self._beta.shape[1]
+        cfg.beta = self._beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        cfg.alpha = (self._alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                     if self._alpha is not None else None)
+        cfg.S = self._S.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        cfg.gamma, cfg.h_km, cfg.L_km = float(gamma), float(h), float(L)
+        cfg.precision, cfg.flags = int(precision), flags
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        handle = ctypes.c_void_p()
+        _check(lib.mmnlse_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(handle)))
+        self._h = handle
+        self.M, self.T, self.dt, self.h, self.L = M, T, dt, h, L
+        self.n_steps = int(round(L / h))
+        self.precision = precision
+
+    @classmethod
+    def from_problem(cls, p, precision: int = FP32, generic: bool = False, L: float | None = None,
+                     stream=None):
+        return cls(p.M, p.T, p.dt, p.beta, p.S, p.gamma, p.h, p.L if L is None else L,
+                   alpha=p.alpha if np.any(p.alpha) else None, precision=precision,
+                   symmetric=p.symmetric, generic=generic, stream=stream)
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mmnlse_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ------------------------------------------------------------------
+    def propagate(self, A, stats: bool = False):
+        """Propagate over L.  numpy input -> numpy output (host path);
+        torch device tensor (complex64/complex128) -> new device tensor."""
+        lib = load()
+        st = Stats()
+        if isinstance(A, np.ndarray):
+            dtype = C128 if A.dtype == np.complex128 else C64
+            src = np.ascontiguousarray(A, dtype=np.complex128 if dtype == C128 else np.complex64)
+            out = np.empty_like(src)
+            _check(lib.mmnlse_propagate(self._h, src.ctypes.data_as(ctypes.c_void_p),
+                                        out.ctypes.data_as(ctypes.c_void_p), dtype, 0, ctypes.byref(st)))
+        else:
+            import torch
+            dtype = C128 if A.dtype == torch.complex128 else C64
+            if A.dtype not in (torch.complex64, torch.complex128) or not A.is_cuda:
+                raise TypeError("expected a complex64/complex128 device tensor")
+            src = A.contiguous()
+            out = torch.empty_like(src)
+            _check(lib.mmnlse_propagate(self._h, ctypes.c_void_p(src.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), dtype, 1, ctypes.byref(st)))
+        if stats:
+            return out, {"power_in": st.power_in, "power_out": st.power_out, "seconds": st.seconds,
+                         "steps": st.steps}
+        return out
+
+    def advance(self, A, n_steps: int):
+        """In-place device advance by n_steps (asynchronous on the plan's stream)."""
+        _check(load().mmnlse_advance(self._h, ctypes.c_void_p(_dptr(A)), int(n_steps)))
+        return A
+
+    def linear_half_step(self, X, Y=None):
+        import torch
+        Y = torch.empty_like(X) if Y is None else Y
+        _check(load().mmnlse_linear_half_step(self._h, ctypes.c_void_p(_dptr(X)), ctypes.c_void_p(_dptr(Y))))
+        return Y
+
+    def kerr(self, X, Y=None):
+        import torch
+        Y = torch.empty_like(X) if Y is None else Y
+        _check(load().mmnlse_kerr(self._h, ctypes.c_void_p(_dptr(X)), ctypes.c_void_p(_dptr(Y))))
+        return Y
+
+    def power(self, X) -> float:
+        out = ctypes.c_double()
+        _check(load().mmnlse_power(self._h, ctypes.c_void_p(_dptr(X)), ctypes.byref(out)))
+        return out.value
+
+    def step_doubling(self, X) -> float:
+        out = ctypes.c_double()
+        _check(load().mmnlse_step_doubling(self._h, ctypes.c_void_p(_dptr(X)), ctypes.byref(out)))
+        return out.value
+
+    def profile(self, A, n_steps: int) -> dict:
+        """Advance A in place by n_steps with HIP events around every launch;
+        returns summed device milliseconds and launch counts per kernel class."""
+        ms = (ctypes.c_double * 2)()
+        cnt = (ctypes.c_int64 * 3)()
+        _check(load().mmnlse_profile(self._h, ctypes.c_void_p(_dptr(A)), int(n_steps), ms, cnt))
+        return {"kerr_ms": ms[0], "linear_ms": ms[1], "kerr_launches": cnt[0],
+                "linear_launches": cnt[1], "kerr_evals": cnt[2]}
+
+    def synchronize(self):
+        _check(load().mmnlse_synchronize(self._h))
+
+    @property
+    def footprint(self) -> int:
+        out = ctypes.c_size_t()
+        _check(load().mmnlse_footprint(self._h, ctypes.byref(out)))
+        return out.value
+
+    @property
+    def kerr_path(self) -> str:
+        out = ctypes.c_int32()
+        _check(load().mmnlse_kerr_path(self._h, ctypes.byref(out)))
+        return KERR_PATHS[out.value]

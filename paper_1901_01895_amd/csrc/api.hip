@@ -1,0 +1,549 @@
+// C-ABI of libmmnlse: plan creation, the RK4IP step schedule and the
+// propagate / advance / component entry points declared in mmnlse.h.
+
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "common.h"
+
+namespace mmnlse {
+
+static thread_local std::string g_err;
+
+static mmnlse_status fail(mmnlse_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+static mmnlse_status hipfail(hipError_t e, const char *what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return MMNLSE_E_DEVICE;
+}
+
+#define HIPCHK(expr, what)                          \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) return hipfail(e_, what); \
+  } while (0)
+
+static int ilog2i(int64_t x) {
+  int r = 0;
+  while ((int64_t(1) << r) < x) ++r;
+  return r;
+}
+
+// Split an FP64 complex value into FP32 hi + lo.
+static inline float4 split_hilo(double re, double im) {
+  const float hr = (float)re, hi = (float)im;
+  return make_float4(hr, hi, (float)(re - (double)hr), (float)(im - (double)hi));
+}
+
+// Tabulate E_p(f) = exp(h/2 * L_p(w_f)) / T in the FFT's storage order;
+// L_p(w) = -alpha_p/2 + i sum_n beta_{n,p} (-w)^n / n! (Eq. 1 in the
+// frequency domain with the exp(-i w t) forward kernel), w_f = 2 pi fftfreq.
+static void tabulate_E(const Plan &pl, double h, std::vector<float4> &E) {
+  const int M = pl.M, T = pl.T;
+  E.resize((size_t)M * T);
+  auto work = [&](int p0, int p1) {
+    std::vector<double> fact(pl.n_beta + 1, 1.0);
+    for (int n = 1; n <= pl.n_beta; ++n) fact[n] = fact[n - 1] * n;
+    for (int p = p0; p < p1; ++p) {
+      const double *b = pl.beta_h + (size_t)p * pl.n_beta;
+      const double a = pl.alpha_h ? pl.alpha_h[p] : 0.0;
+      for (int pos = 0; pos < T; ++pos) {
+        int f = pos;
+        if (pl.four_step) {  // position N2*k1 + k2 holds bin k1 + N1*k2
+          const int k1 = pos / pl.N2, k2 = pos % pl.N2;
+          f = k1 + pl.N1 * k2;
+        }
+        const double freq = (f < (T + 1) / 2 ? (double)f : (double)(f - T)) / ((double)T * pl.dt);
+        const double w = 2.0 * M_PI * freq;
+        double phase = 0.0, pw = 1.0;
+        for (int n = 0; n < pl.n_beta; ++n) {
+          phase += b[n] * pw / fact[n];
+          pw *= -w;
+        }
+        const double mag = std::exp(-0.25 * h * a) / (double)T;
+        const double ang = 0.5 * h * phase;
+        E[(size_t)p * T + pos] = split_hilo(mag * std::cos(ang), mag * std::sin(ang));
+      }
+    }
+  };
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (M < 2 || (size_t)M * T < (1u << 16)) nth = 1;
+  std::vector<std::thread> th;
+  for (unsigned i = 0; i < nth; ++i) {
+    const int p0 = (int)((int64_t)M * i / nth), p1 = (int)((int64_t)M * (i + 1) / nth);
+    if (p1 > p0) th.emplace_back(work, p0, p1);
+  }
+  for (auto &t : th) t.join();
+}
+
+static hipError_t dev_alloc(Plan &pl, void **p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e == hipSuccess) pl.bytes += bytes;
+  return e;
+}
+
+static void free_plan(Plan *pl) {
+  if (!pl) return;
+  hipFree(pl->tw);
+  hipFree(pl->E);
+  hipFree(pl->E2);
+  hipFree(pl->Sg);
+  hipFree(pl->Sp);
+  hipFree(pl->Sph);
+  hipFree(pl->Spl);
+  hipFree(pl->pairs);
+  for (auto &b : pl->buf) hipFree(b);
+  for (auto &b : pl->sd) hipFree(b);
+  hipFree(pl->red);
+  delete[] pl->beta_h;
+  delete[] pl->alpha_h;
+  delete pl;
+}
+
+// The RK4IP step of Eq. (6a-f) as five fused launches (nine when the FFT is
+// four-step), over the state A and two work fields:
+//   (pre)  W0 = h N(A)                                   k1 before dispersion
+//   F_a    A <- D A (=A_I),  W0 <- D W0 (=k1)            Eq. 6a, 6b
+//   K_2    W1 = h N(A_I + k1/2)                          Eq. 6c
+//   K_3    k3 = h N(A_I + k2/2); W0 <- A_I + k3;
+//          W1 <- A_I + k1/6 + k2/3 + k3/3                Eq. 6d and the 6f sum
+//   F_b    W0 <- D W0,  W1 <- D W1                       Eq. 6e, 6f
+//   K_4    k4 = h N(W0); A <- W1 + k4/6                  Eq. 6e, 6f
+//          and, unless last, W0 = h N(A) for the next step.
+hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float4 *E,
+                     float2 *const *work, Prof *prof) {
+  if (n_steps <= 0) return hipSuccess;
+  float2 *W0 = work[0], *W1 = work[1];
+  hipError_t e;
+  auto kerr = [&](const KerrLaunch &k) -> hipError_t {
+    if (prof && (e = prof->record(prof->kerr, pl.stream)) != hipSuccess) return e;
+    if ((e = launch_kerr(pl, h, k)) != hipSuccess) return e;
+    if (prof) {
+      prof->kerr_evals += (k.stage == STAGE_K4 && k.next) ? 2 : 1;
+      return prof->record(prof->kerr, pl.stream);
+    }
+    return hipSuccess;
+  };
+  auto linear = [&](float2 *a, float2 *b) -> hipError_t {
+    if (prof && (e = prof->record(prof->lin, pl.stream)) != hipSuccess) return e;
+    if ((e = launch_linear(pl, E, a, a, b, b)) != hipSuccess) return e;
+    return prof ? prof->record(prof->lin, pl.stream) : hipSuccess;
+  };
+  KerrLaunch k{};
+  k.stage = STAGE_PLAIN;
+  k.src0 = A;
+  k.out0 = W0;
+  if ((e = kerr(k)) != hipSuccess) return e;
+  for (int64_t s = 0; s < n_steps; ++s) {
+    if ((e = linear(A, W0)) != hipSuccess) return e;
+    k = KerrLaunch{};
+    k.stage = STAGE_K2;
+    k.src0 = A;
+    k.src1 = W0;
+    k.out0 = W1;
+    if ((e = kerr(k)) != hipSuccess) return e;
+    k = KerrLaunch{};
+    k.stage = STAGE_K3;
+    k.src0 = A;
+    k.src1 = W0;
+    k.src2 = W1;
+    k.out0 = W0;
+    k.out1 = W1;
+    if ((e = kerr(k)) != hipSuccess) return e;
+    if ((e = linear(W0, W1)) != hipSuccess) return e;
+    k = KerrLaunch{};
+    k.stage = STAGE_K4;
+    k.src0 = W0;
+    k.src1 = W1;
+    k.out0 = A;
+    k.out1 = W0;
+    k.next = (s + 1 < n_steps) ? 1 : 0;
+    if ((e = kerr(k)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+static bool check_symmetric(const float *S, int M, double tol, std::string &why) {
+  double smax = 0.0;
+  const size_t n4 = (size_t)M * M * M * M;
+  for (size_t i = 0; i < n4; ++i) smax = std::max(smax, (double)std::fabs(S[i]));
+  const double lim = tol * (smax > 0 ? smax : 1.0);
+  auto at = [&](int p, int l, int m, int n) { return (double)S[(((size_t)p * M + l) * M + m) * M + n]; };
+  for (int p = 0; p < M; ++p)
+    for (int l = 0; l < M; ++l)
+      for (int m = 0; m < M; ++m)
+        for (int n = 0; n < M; ++n) {
+          const double v = at(p, l, m, n);
+          if (std::fabs(v - at(p, m, l, n)) > lim) {
+            why = "S is not symmetric in (l,m)";
+            return false;
+          }
+          if (std::fabs(v - at(n, l, m, p)) > lim) {
+            why = "S is not symmetric in (p,n)";
+            return false;
+          }
+        }
+  return true;
+}
+
+hipError_t setup_mfma(Plan &pl, const float *S);  // kerr_mfma.hip
+
+}  // namespace mmnlse
+
+using namespace mmnlse;
+
+struct mmnlse_ctx {
+  Plan *pl;
+};
+
+extern "C" {
+
+const char *mmnlse_last_error(void) { return g_err.c_str(); }
+
+mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *out) {
+  g_err.clear();
+  if (!cfg || !out) return fail(MMNLSE_E_INVALID, "null argument");
+  *out = nullptr;
+  const int M = cfg->M, T = cfg->T;
+  if (M < 1 || M > 256) return fail(MMNLSE_E_INVALID, "M must be in [1, 256]");
+  if (T < 64 || T > (1 << 20) || (T & (T - 1))) return fail(MMNLSE_E_INVALID, "T must be a power of two in [64, 2^20]");
+  if (!(cfg->dt_ps > 0) || !std::isfinite(cfg->dt_ps)) return fail(MMNLSE_E_INVALID, "dt must be positive");
+  if (cfg->n_beta < 0 || cfg->n_beta > 8) return fail(MMNLSE_E_INVALID, "n_beta must be in [0, 8]");
+  if (cfg->n_beta > 0 && !cfg->beta) return fail(MMNLSE_E_INVALID, "beta is NULL");
+  if (!cfg->S) return fail(MMNLSE_E_INVALID, "S is NULL");
+  if (!std::isfinite(cfg->gamma)) return fail(MMNLSE_E_INVALID, "gamma must be finite");
+  if (!(cfg->h_km > 0) || !std::isfinite(cfg->h_km)) return fail(MMNLSE_E_INVALID, "h must be positive");
+  if (!(cfg->L_km >= 0) || !std::isfinite(cfg->L_km)) return fail(MMNLSE_E_INVALID, "L must be >= 0");
+  const double ratio = cfg->L_km / cfg->h_km;
+  const double nst = std::round(ratio);
+  if (std::fabs(ratio - nst) > 1e-9 * std::max(1.0, ratio)) return fail(MMNLSE_E_INVALID, "L/h is not an integer");
+  if (cfg->precision != MMNLSE_FP32 && cfg->precision != MMNLSE_SPLIT_BF16)
+    return fail(MMNLSE_E_INVALID, "unknown precision");
+  for (int i = 0; i < M * cfg->n_beta; ++i)
+    if (!std::isfinite(cfg->beta[i])) return fail(MMNLSE_E_INVALID, "beta is not finite");
+  if (cfg->alpha)
+    for (int i = 0; i < M; ++i)
+      if (!std::isfinite(cfg->alpha[i])) return fail(MMNLSE_E_INVALID, "alpha is not finite");
+  const size_t n4 = (size_t)M * M * M * M;
+  for (size_t i = 0; i < n4; ++i)
+    if (!std::isfinite(cfg->S[i])) return fail(MMNLSE_E_INVALID, "S is not finite");
+  const bool sym = (cfg->flags & MMNLSE_S_SYMMETRIC) != 0;
+  if (sym) {
+    std::string why;
+    if (!check_symmetric(cfg->S, M, 1e-6, why)) return fail(MMNLSE_E_INVALID, why + " but MMNLSE_S_SYMMETRIC is set");
+  }
+  if (cfg->precision == MMNLSE_SPLIT_BF16 && !sym)
+    return fail(MMNLSE_E_INVALID, "split-bf16 precision needs MMNLSE_S_SYMMETRIC");
+
+  Plan *pl = new (std::nothrow) Plan();
+  if (!pl) return fail(MMNLSE_E_NOMEM, "host allocation");
+  pl->M = M;
+  pl->T = T;
+  pl->logT = ilog2i(T);
+  pl->dt = cfg->dt_ps;
+  pl->h = cfg->h_km;
+  pl->L = cfg->L_km;
+  pl->gamma = cfg->gamma;
+  pl->n_steps = (int64_t)nst;
+  pl->n_beta = cfg->n_beta;
+  pl->precision = cfg->precision;
+  pl->flags = cfg->flags;
+  pl->stream = (hipStream_t)stream;
+  hipGetDevice(&pl->device);
+  const char *force4 = std::getenv("MMNLSE_FORCE_FOUR_STEP");
+  pl->four_step = T > 16384 || (force4 && force4[0] == '1' && T >= 1024);
+  if (pl->four_step) {
+    pl->N1 = 1 << (pl->logT / 2);
+    pl->N2 = T / pl->N1;
+  }
+  pl->beta_h = new double[(size_t)M * std::max(1, cfg->n_beta)];
+  if (cfg->n_beta) std::memcpy(pl->beta_h, cfg->beta, sizeof(double) * M * cfg->n_beta);
+  if (cfg->alpha) {
+    pl->alpha_h = new double[M];
+    std::memcpy(pl->alpha_h, cfg->alpha, sizeof(double) * M);
+  }
+
+  // Kerr path
+  const bool force_generic = (cfg->flags & MMNLSE_KERR_GENERIC) != 0;
+  const char *fpath = std::getenv("MMNLSE_KERR_PATH");
+  if (cfg->precision == MMNLSE_SPLIT_BF16) pl->kerr_path = KERR_MFMA;
+  else if (force_generic) pl->kerr_path = KERR_GENERIC;
+  else if (M <= 8) pl->kerr_path = KERR_SMALL;
+  else pl->kerr_path = KERR_GENERIC;
+  if (fpath && !force_generic && cfg->precision == MMNLSE_FP32) {
+    const int v = std::atoi(fpath);
+    if (v == KERR_SMALL && M <= 8) pl->kerr_path = KERR_SMALL;
+    if (v == KERR_GENERIC) pl->kerr_path = KERR_GENERIC;
+    if (v == KERR_MFMA && sym) pl->kerr_path = KERR_MFMA;
+  }
+  if (pl->kerr_path == KERR_GENERIC && M > 128) {
+    free_plan(pl);
+    return fail(MMNLSE_E_UNSUPPORTED, "generic Kerr kernel supports M <= 128 (use a symmetric S)");
+  }
+
+  hipError_t e;
+  const size_t MT = (size_t)M * T;
+  // twiddles
+  {
+    std::vector<float4> tw(T);
+    for (int j = 0; j < T; ++j) {
+      const double ang = -2.0 * M_PI * (double)j / (double)T;
+      tw[j] = split_hilo(std::cos(ang), std::sin(ang));
+    }
+    if ((e = dev_alloc(*pl, (void **)&pl->tw, sizeof(float4) * T)) != hipSuccess) goto nomem;
+    if ((e = hipMemcpy(pl->tw, tw.data(), sizeof(float4) * T, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
+  }
+  {
+    std::vector<float4> E;
+    tabulate_E(*pl, pl->h, E);
+    if ((e = dev_alloc(*pl, (void **)&pl->E, sizeof(float4) * MT)) != hipSuccess) goto nomem;
+    if ((e = hipMemcpy(pl->E, E.data(), sizeof(float4) * MT, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
+  }
+  if (pl->kerr_path != KERR_MFMA) {
+    std::vector<float> Sg(n4);
+    for (int p = 0; p < M; ++p)
+      for (int l = 0; l < M; ++l)
+        for (int m = 0; m < M; ++m)
+          for (int n = 0; n < M; ++n)
+            Sg[(((size_t)p * M + n) * M + m) * M + l] = cfg->S[(((size_t)p * M + l) * M + m) * M + n];
+    if ((e = dev_alloc(*pl, (void **)&pl->Sg, sizeof(float) * n4)) != hipSuccess) goto nomem;
+    if ((e = hipMemcpy(pl->Sg, Sg.data(), sizeof(float) * n4, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
+  } else {
+    if ((e = setup_mfma(*pl, cfg->S)) != hipSuccess) {
+      if (e == hipErrorOutOfMemory) goto nomem;
+      if (e == hipErrorNotSupported) {
+        free_plan(pl);
+        return fail(MMNLSE_E_UNSUPPORTED, "matrix-core Kerr path not available in this build");
+      }
+      goto dev;
+    }
+  }
+  for (auto &b : pl->buf)
+    if ((e = dev_alloc(*pl, (void **)&b, sizeof(float2) * MT)) != hipSuccess) goto nomem;
+  pl->red_n = (int)std::min<size_t>(1024, std::max<size_t>(1, MT / 4096));
+  if ((e = dev_alloc(*pl, (void **)&pl->red, sizeof(double2) * 1024)) != hipSuccess) goto nomem;
+  {
+    mmnlse_ctx *c = new (std::nothrow) mmnlse_ctx{pl};
+    if (!c) {
+      free_plan(pl);
+      return fail(MMNLSE_E_NOMEM, "host allocation");
+    }
+    *out = c;
+  }
+  return MMNLSE_OK;
+nomem:
+  free_plan(pl);
+  (void)hipGetLastError();
+  return fail(MMNLSE_E_NOMEM, "device allocation failed");
+dev:
+  free_plan(pl);
+  return hipfail(e, "create");
+}
+
+mmnlse_status mmnlse_destroy(mmnlse_t h) {
+  if (!h) return MMNLSE_OK;
+  if (h->pl && h->pl->stream) hipStreamSynchronize(h->pl->stream);
+  else hipDeviceSynchronize();
+  free_plan(h->pl);
+  delete h;
+  return MMNLSE_OK;
+}
+
+mmnlse_status mmnlse_advance(mmnlse_t h, void *A, int64_t n_steps) {
+  g_err.clear();
+  if (!h || !A) return fail(MMNLSE_E_INVALID, "null argument");
+  if (n_steps < 0) return fail(MMNLSE_E_INVALID, "n_steps < 0");
+  Plan &pl = *h->pl;
+  hipError_t e = run_steps(pl, (float2 *)A, n_steps, pl.h, pl.E, pl.buf);
+  if (e != hipSuccess) return hipfail(e, "advance");
+  return MMNLSE_OK;
+}
+
+mmnlse_status mmnlse_propagate(mmnlse_t h, const void *A_in, void *A_out, int32_t dtype, int32_t on_device,
+                               mmnlse_stats *st) {
+  g_err.clear();
+  if (!h || !A_in || !A_out) return fail(MMNLSE_E_INVALID, "null argument");
+  if (dtype != MMNLSE_C64 && dtype != MMNLSE_C128) return fail(MMNLSE_E_INVALID, "unknown dtype");
+  Plan &pl = *h->pl;
+  const size_t MT = (size_t)pl.M * pl.T;
+  float2 *state = pl.buf[2];
+  double2 *stage128 = nullptr;
+  struct Guard {
+    double2 *&p;
+    ~Guard() { if (p) hipFree(p); }
+  } guard{stage128};
+  if (dtype == MMNLSE_C128 && !on_device)
+    HIPCHK(hipMalloc(&stage128, sizeof(double2) * MT), "staging alloc");
+  if (dtype == MMNLSE_C64) {
+    if (on_device) {
+      // run in place on A_out
+      if (A_out != A_in)
+        HIPCHK(hipMemcpyAsync(A_out, A_in, sizeof(float2) * MT, hipMemcpyDeviceToDevice, pl.stream), "copy");
+      state = (float2 *)A_out;
+    } else {
+      HIPCHK(hipMemcpyAsync(state, A_in, sizeof(float2) * MT, hipMemcpyHostToDevice, pl.stream), "upload");
+    }
+  } else {
+    const double2 *src = (const double2 *)A_in;
+    if (!on_device) {
+      HIPCHK(hipMemcpyAsync(stage128, A_in, sizeof(double2) * MT, hipMemcpyHostToDevice, pl.stream), "upload");
+      src = stage128;
+    }
+    HIPCHK(launch_convert_c128_to_c64(pl, src, state, MT), "convert");
+  }
+  double p_in = 0, p_out = 0;
+  HIPCHK(reduce_norms(pl, state, nullptr, MT, &p_in, nullptr), "power");
+  if (!std::isfinite(p_in)) return fail(MMNLSE_E_NONFINITE, "input field is not finite");
+  const auto t0 = std::chrono::steady_clock::now();
+  hipError_t e = run_steps(pl, state, pl.n_steps, pl.h, pl.E, pl.buf);
+  if (e == hipSuccess) e = hipStreamSynchronize(pl.stream);
+  const auto t1 = std::chrono::steady_clock::now();
+  if (e != hipSuccess) return hipfail(e, "steps");
+  HIPCHK(reduce_norms(pl, state, nullptr, MT, &p_out, nullptr), "power");
+  if (dtype == MMNLSE_C64) {
+    if (!on_device)
+      HIPCHK(hipMemcpyAsync(A_out, state, sizeof(float2) * MT, hipMemcpyDeviceToHost, pl.stream), "download");
+  } else {
+    double2 *dst = on_device ? (double2 *)A_out : stage128;
+    HIPCHK(launch_convert_c64_to_c128(pl, state, dst, MT), "convert");
+    if (!on_device)
+      HIPCHK(hipMemcpyAsync(A_out, stage128, sizeof(double2) * MT, hipMemcpyDeviceToHost, pl.stream), "download");
+  }
+  HIPCHK(hipStreamSynchronize(pl.stream), "download");
+  p_in *= pl.dt;
+  p_out *= pl.dt;
+  if (st) {
+    st->power_in = p_in;
+    st->power_out = p_out;
+    st->seconds = std::chrono::duration<double>(t1 - t0).count();
+    st->steps = pl.n_steps;
+  }
+  if (!std::isfinite(p_out)) return fail(MMNLSE_E_NONFINITE, "result is not finite");
+  return MMNLSE_OK;
+}
+
+mmnlse_status mmnlse_linear_half_step(mmnlse_t h, const void *X, void *Y) {
+  g_err.clear();
+  if (!h || !X || !Y) return fail(MMNLSE_E_INVALID, "null argument");
+  Plan &pl = *h->pl;
+  hipError_t e = launch_linear(pl, pl.E, (const float2 *)X, (float2 *)Y, nullptr, nullptr);
+  if (e != hipSuccess) return hipfail(e, "linear");
+  return MMNLSE_OK;
+}
+
+mmnlse_status mmnlse_kerr(mmnlse_t h, const void *X, void *Y) {
+  g_err.clear();
+  if (!h || !X || !Y) return fail(MMNLSE_E_INVALID, "null argument");
+  if (X == Y) return fail(MMNLSE_E_INVALID, "Y must not alias X");
+  Plan &pl = *h->pl;
+  KerrLaunch k{};
+  k.stage = STAGE_PLAIN;
+  k.src0 = (const float2 *)X;
+  k.out0 = (float2 *)Y;
+  hipError_t e = launch_kerr(pl, pl.h, k);
+  if (e != hipSuccess) return hipfail(e, "kerr");
+  return MMNLSE_OK;
+}
+
+mmnlse_status mmnlse_power(mmnlse_t h, const void *X, double *out) {
+  g_err.clear();
+  if (!h || !X || !out) return fail(MMNLSE_E_INVALID, "null argument");
+  Plan &pl = *h->pl;
+  double s = 0;
+  hipError_t e = reduce_norms(pl, (const float2 *)X, nullptr, (size_t)pl.M * pl.T, &s, nullptr);
+  if (e != hipSuccess) return hipfail(e, "power");
+  *out = s * pl.dt;
+  return MMNLSE_OK;
+}
+
+mmnlse_status mmnlse_step_doubling(mmnlse_t h, const void *X, double *delta) {
+  g_err.clear();
+  if (!h || !X || !delta) return fail(MMNLSE_E_INVALID, "null argument");
+  Plan &pl = *h->pl;
+  const size_t MT = (size_t)pl.M * pl.T;
+  hipError_t e;
+  if (!pl.E2) {
+    std::vector<float4> E2;
+    tabulate_E(pl, 2.0 * pl.h, E2);
+    if ((e = dev_alloc(pl, (void **)&pl.E2, sizeof(float4) * MT)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MMNLSE_E_NOMEM, "device allocation failed");
+    }
+    HIPCHK(hipMemcpy(pl.E2, E2.data(), sizeof(float4) * MT, hipMemcpyHostToDevice), "upload");
+  }
+  for (auto &b : pl.sd)
+    if (!b && (e = dev_alloc(pl, (void **)&b, sizeof(float2) * MT)) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(MMNLSE_E_NOMEM, "device allocation failed");
+    }
+  float2 *fine = pl.sd[0], *coarse = pl.sd[1];
+  HIPCHK(hipMemcpyAsync(fine, X, sizeof(float2) * MT, hipMemcpyDeviceToDevice, pl.stream), "copy");
+  HIPCHK(hipMemcpyAsync(coarse, X, sizeof(float2) * MT, hipMemcpyDeviceToDevice, pl.stream), "copy");
+  float2 *work[2] = {pl.buf[0], pl.buf[1]};
+  HIPCHK(run_steps(pl, fine, 2, pl.h, pl.E, work), "fine steps");
+  HIPCHK(run_steps(pl, coarse, 1, 2.0 * pl.h, pl.E2, work), "coarse step");
+  double sf = 0, sd = 0;
+  HIPCHK(reduce_norms(pl, fine, coarse, MT, &sf, &sd), "norms");
+  *delta = sf > 0 ? std::sqrt(sd / sf) : 0.0;
+  return MMNLSE_OK;
+}
+
+mmnlse_status mmnlse_profile(mmnlse_t h, void *A, int64_t n_steps, double *ms, int64_t *counts) {
+  g_err.clear();
+  if (!h || !A || !ms || !counts) return fail(MMNLSE_E_INVALID, "null argument");
+  if (n_steps < 0) return fail(MMNLSE_E_INVALID, "n_steps < 0");
+  Plan &pl = *h->pl;
+  Prof prof;
+  hipError_t e = run_steps(pl, (float2 *)A, n_steps, pl.h, pl.E, pl.buf, &prof);
+  if (e == hipSuccess) e = hipStreamSynchronize(pl.stream);
+  double tk = 0, tl = 0;
+  for (size_t i = 0; e == hipSuccess && i + 1 < prof.kerr.size(); i += 2) {
+    float t = 0;
+    e = hipEventElapsedTime(&t, prof.kerr[i], prof.kerr[i + 1]);
+    tk += t;
+  }
+  for (size_t i = 0; e == hipSuccess && i + 1 < prof.lin.size(); i += 2) {
+    float t = 0;
+    e = hipEventElapsedTime(&t, prof.lin[i], prof.lin[i + 1]);
+    tl += t;
+  }
+  for (auto ev : prof.kerr) hipEventDestroy(ev);
+  for (auto ev : prof.lin) hipEventDestroy(ev);
+  if (e != hipSuccess) return hipfail(e, "profile");
+  ms[0] = tk;
+  ms[1] = tl;
+  counts[0] = (int64_t)prof.kerr.size() / 2;
+  counts[1] = (int64_t)prof.lin.size() / 2;
+  counts[2] = prof.kerr_evals;
+  return MMNLSE_OK;
+}
+
+mmnlse_status mmnlse_synchronize(mmnlse_t h) {
+  g_err.clear();
+  if (!h) return fail(MMNLSE_E_INVALID, "null argument");
+  HIPCHK(hipStreamSynchronize(h->pl->stream), "synchronize");
+  return MMNLSE_OK;
+}
+
+mmnlse_status mmnlse_footprint(const mmnlse_t h, size_t *bytes) {
+  if (!h || !bytes) return fail(MMNLSE_E_INVALID, "null argument");
+  *bytes = h->pl->bytes;
+  return MMNLSE_OK;
+}
+
+mmnlse_status mmnlse_kerr_path(const mmnlse_t h, int32_t *path) {
+  if (!h || !path) return fail(MMNLSE_E_INVALID, "null argument");
+  *path = h->pl->kerr_path;
+  return MMNLSE_OK;
+}
+
+}  // extern "C"

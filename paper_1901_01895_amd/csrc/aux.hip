@@ -1,0 +1,86 @@
+// Field conversions and the FP64 reductions used for the power invariant
+// (total power dt*sum|A|^2 is conserved by Eq. 1 when alpha = 0 and the
+// Kerr tensor satisfies S_plmn == S_lpnm) and the step-doubling estimate.
+
+#include "common.h"
+
+namespace mmnlse {
+namespace {
+
+__global__ void c128_to_c64(const double2 *__restrict__ in, float2 *__restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = make_float2((float)in[i].x, (float)in[i].y);
+}
+
+__global__ void c64_to_c128(const float2 *__restrict__ in, double2 *__restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = make_double2((double)in[i].x, (double)in[i].y);
+}
+
+constexpr int RB = 256;
+
+// partial[b] = (sum |x|^2, sum |x - y|^2) over a grid-stride slice, in FP64
+__global__ __launch_bounds__(RB) void norms(const float2 *__restrict__ x, const float2 *__restrict__ y,
+                                            size_t n, double2 *__restrict__ partial) {
+  double sx = 0.0, sd = 0.0;
+  for (size_t i = (size_t)blockIdx.x * RB + threadIdx.x; i < n; i += (size_t)gridDim.x * RB) {
+    const float2 v = x[i];
+    sx = fma((double)v.x, (double)v.x, fma((double)v.y, (double)v.y, sx));
+    if (y) {
+      const float2 u = y[i];
+      const double dx = (double)v.x - (double)u.x, dy = (double)v.y - (double)u.y;
+      sd = fma(dx, dx, fma(dy, dy, sd));
+    }
+  }
+  __shared__ double2 red[RB];
+  red[threadIdx.x] = make_double2(sx, sd);
+  __syncthreads();
+  for (int s = RB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[threadIdx.x].x += red[threadIdx.x + s].x;
+      red[threadIdx.x].y += red[threadIdx.x + s].y;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+int grid_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (int)(b < 4096 ? (b ? b : 1) : 4096);
+}
+
+}  // namespace
+
+hipError_t launch_convert_c128_to_c64(const Plan &pl, const double2 *in, float2 *out, size_t n) {
+  hipLaunchKernelGGL(c128_to_c64, dim3(grid_for(n)), dim3(256), 0, pl.stream, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert_c64_to_c128(const Plan &pl, const float2 *in, double2 *out, size_t n) {
+  hipLaunchKernelGGL(c64_to_c128, dim3(grid_for(n)), dim3(256), 0, pl.stream, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t reduce_norms(const Plan &pl, const float2 *x, const float2 *y, size_t n, double *sx,
+                        double *sxy) {
+  const int nb = pl.red_n;
+  hipLaunchKernelGGL(norms, dim3(nb), dim3(RB), 0, pl.stream, x, y, n, (double2 *)pl.red);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  double2 host[1024];
+  e = hipMemcpyAsync(host, pl.red, sizeof(double2) * nb, hipMemcpyDeviceToHost, pl.stream);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(pl.stream);
+  if (e != hipSuccess) return e;
+  double a = 0.0, b = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    a += host[i].x;
+    b += host[i].y;
+  }
+  if (sx) *sx = a;
+  if (sxy) *sxy = b;
+  return hipSuccess;
+}
+
+}  // namespace mmnlse

@@ -1,0 +1,142 @@
+// Internal declarations shared by the HIP sources of libmmnlse.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "mmnlse.h"
+
+namespace mmnlse {
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+
+// a * (w_hi + w_lo) with w = (hi.re, hi.im, lo.re, lo.im): the small lo
+// product is folded in before the hi product is rounded, so the twiddle or
+// propagator factor acts as if it were exact and rounding stays unbiased.
+__device__ __forceinline__ float2 cmul_hilo(float2 a, float4 w) {
+  float cre = a.x * w.z - a.y * w.w;
+  float cim = a.x * w.w + a.y * w.z;
+  float re = fmaf(a.x, w.x, fmaf(-a.y, w.y, cre));
+  float im = fmaf(a.x, w.y, fmaf(a.y, w.x, cim));
+  return make_float2(re, im);
+}
+
+__device__ __forceinline__ float4 conj_hilo(float4 w) { return make_float4(w.x, -w.y, w.z, -w.w); }
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// a + s*b
+__device__ __forceinline__ float2 caxpy(float2 a, float s, float2 b) {
+  return make_float2(fmaf(s, b.x, a.x), fmaf(s, b.y, a.y));
+}
+// acc + a*b (complex)
+__device__ __forceinline__ float2 cfma(float2 acc, float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y)));
+}
+// acc + a*conj(b)
+__device__ __forceinline__ float2 cfma_conj(float2 acc, float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, fmaf(a.y, b.y, acc.x)), fmaf(a.y, b.x, fmaf(-a.x, b.y, acc.y)));
+}
+
+// ---------------------------------------------------------------------------
+// host-side plan
+// ---------------------------------------------------------------------------
+
+enum KerrPath : int32_t { KERR_SMALL = 0, KERR_GENERIC = 1, KERR_MFMA = 2 };
+
+// Which fields a Kerr launch reads and writes (the RK4 combinations of Eq. 6
+// fused into the kernel's prologue and epilogue).
+enum KerrStage : int32_t {
+  // out0 = h N(src0)
+  STAGE_PLAIN = 0,
+  // X = src0 + src2/2 (A_I + k2/2); k3 = h N(X);
+  // out0 = src0 + k3 (A_I + k3), out1 = src0 + src1/6 + src2/3 + k3/3
+  STAGE_K3 = 1,
+  // k4 = h N(src0) (src0 = D(A_I + k3)); A = src1 + k4/6 -> out0;
+  // if `next`, out1 = h N(A) (k1 input of the following step)
+  STAGE_K4 = 2,
+  // X = src0 + src1/2 (A_I + k1/2); out0 = h N(X)
+  STAGE_K2 = 3,
+};
+
+struct KerrLaunch {
+  KerrStage stage;
+  const float2 *src0, *src1, *src2;
+  float2 *out0, *out1;
+  int next;  // STAGE_K4: also evaluate h N(A)
+};
+
+struct Plan {
+  // problem
+  int M = 0, T = 0, logT = 0;
+  double dt = 0, h = 0, gamma = 0, L = 0;
+  int64_t n_steps = 0;
+  int n_beta = 0;
+  int precision = MMNLSE_FP32;
+  uint32_t flags = 0;
+  KerrPath kerr_path = KERR_GENERIC;
+  // FFT decomposition: single pass in LDS when !four_step, else T = N1 * N2
+  bool four_step = false;
+  int N1 = 0, N2 = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+
+  // host copies of the coefficients (for re-tabulation at other step sizes)
+  double *beta_h = nullptr;   // [M][n_beta]
+  double *alpha_h = nullptr;  // [M]
+
+  // device tables
+  float4 *tw = nullptr;   // [T] exp(-2 pi i j / T) as FP32 hi + lo
+  float4 *E = nullptr;    // [M][T] exp(h/2 L)/T as hi + lo, in the FFT's storage order
+  float4 *E2 = nullptr;   // same for step 2h (step doubling), built on first use
+  float *Sg = nullptr;    // generic tensor layout [p][n][m][l]
+  // packed symmetric tensor (matrix-core path): rows r = (p<=n), cols q = (l<=m)
+  int P = 0, Ppad = 0;
+  float *Sp = nullptr;          // [Ppad][Ppad] FP32, weight 2 for l<m folded in
+  uint16_t *Sph = nullptr;      // bf16 hi of Sp
+  uint16_t *Spl = nullptr;      // bf16 lo of Sp - hi
+  int32_t *pairs = nullptr;     // [Ppad] packed (a | b << 16) for r / q index -> (a,b)
+
+  // workspace
+  float2 *buf[3] = {nullptr, nullptr, nullptr};
+  float2 *sd[3] = {nullptr, nullptr, nullptr};  // step-doubling workspace (lazy)
+  double *red = nullptr;   // reduction partials
+  int red_n = 0;
+  size_t bytes = 0;
+};
+
+// kernels (launch wrappers); all asynchronous on plan.stream
+hipError_t launch_linear(const Plan &pl, const float4 *E, const float2 *in0, float2 *out0,
+                         const float2 *in1, float2 *out1);
+hipError_t launch_kerr(const Plan &pl, double h, const KerrLaunch &k);
+hipError_t launch_convert_c128_to_c64(const Plan &pl, const double2 *in, float2 *out, size_t n);
+hipError_t launch_convert_c64_to_c128(const Plan &pl, const float2 *in, double2 *out, size_t n);
+// FP64 sum of |x|^2 (and of |x - y|^2 when y != nullptr) -> host values (synchronises)
+hipError_t reduce_norms(const Plan &pl, const float2 *x, const float2 *y, size_t n, double *sx,
+                        double *sxy);
+hipError_t launch_pack_bf16(const Plan &pl);
+
+// optional per-launch event pairs (measurement only)
+struct Prof {
+  std::vector<hipEvent_t> kerr, lin;  // start/stop pairs, in launch order
+  int64_t kerr_evals = 0;
+  hipError_t record(std::vector<hipEvent_t> &v, hipStream_t s) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    v.push_back(e);
+    return hipEventRecord(e, s);
+  }
+};
+
+// the RK4IP step schedule
+hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float4 *E,
+                     float2 *const *work, Prof *prof = nullptr);
+
+}  // namespace mmnlse

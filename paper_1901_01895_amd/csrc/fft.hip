@@ -1,0 +1,288 @@
+// Half-step linear propagator D = exp(h/2 L) applied per mode in the
+// frequency domain (Eq. 6a, 6b, 6e, 6f; Section 3.1 of the paper):
+// forward FFT -> multiply by E = exp(h/2 L)/T -> inverse FFT.
+//
+// FFTs are Stockham radix-4 (plus one radix-2 stage for odd log2 sizes) on
+// data staged in LDS, FP32 arithmetic.  Every twiddle and every propagator
+// factor is an FP32 hi + lo pair tabulated in FP64, multiplied with
+// cmul_hilo, so no factor carries a fixed rounding bias from one step to the
+// next (a biased twiddle turns into a gain error that grows linearly with the
+// number of round trips).
+//
+// T <= 2^14: one workgroup transforms whole rows in LDS, multiplies and
+// transforms back (one HBM read + one write per field).
+// T >= 2^15 (or when forced): four-step with T = N1*N2, time index
+// n = N2*n1 + n2, frequency f = k1 + N1*k2:
+//   pass A: per column n2, FFT over n1 (stride N2), times W_T^(n2*k1)
+//   pass B: per row k1, FFT over n2 (contiguous), times E (tabulated in this
+//           transposed bin order), inverse FFT over k2
+//   pass C: times W_T^(-n2*k1), inverse FFT over k1 per column
+// All passes work in place, each workgroup owning disjoint elements.
+
+#include "common.h"
+
+namespace mmnlse {
+namespace {
+
+constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2 &a0, float2 &a1, float2 &a2, float2 &a3) {
+  float2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3), t3 = csub(a1, a3);
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  // forward: W4 = -i, so y1 = t1 - i t3, y3 = t1 + i t3; inverse swaps them
+  float2 mi_t3 = make_float2(t3.y, -t3.x);
+  if (!INV) {
+    a1 = cadd(t1, mi_t3);
+    a3 = csub(t1, mi_t3);
+  } else {
+    a1 = csub(t1, mi_t3);
+    a3 = cadd(t1, mi_t3);
+  }
+}
+
+// One Stockham stage of radix R on NB sequences of length L in LDS.
+// Element i of sequence b lives at buf[b*BS + i*ES].  Ns = size of the
+// sub-transforms already done; twiddle W_{Ns*R}^(r*k) = W_T^((r*k) << sh)
+// with sh = logT - log2(Ns*R).
+template <int R, int L, int NB, int ES, int BS, int NT, bool INV>
+__device__ __forceinline__ void stockham_stage(float2 *buf, int Ns, int sh,
+                                               const float4 *__restrict__ tw) {
+  constexpr int U = NB * (L / R);
+  constexpr int PER = (U + NT - 1) / NT;
+  float2 v[PER][R];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int u = tid + q * NT;
+    if (PER * NT == U || u < U) {
+      int j, b;
+      if (ES == 1) { j = u % (L / R); b = u / (L / R); }
+      else { b = u % NB; j = u / NB; }
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = buf[b * BS + (j + r * (L / R)) * ES];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int u = tid + q * NT;
+    if (PER * NT == U || u < U) {
+      int j, b;
+      if (ES == 1) { j = u % (L / R); b = u / (L / R); }
+      else { b = u % NB; j = u / NB; }
+      const int k = j & (Ns - 1);
+      if (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float4 w = tw[(r * k) << sh];
+          if (INV) w = conj_hilo(w);
+          v[q][r] = cmul_hilo(v[q][r], w);
+        }
+      }
+      if (R == 4) {
+        dft4<INV>(v[q][0], v[q][1], v[q][2], v[q][3]);
+      } else {
+        float2 a = v[q][0], c = v[q][1];
+        v[q][0] = cadd(a, c);
+        v[q][1] = csub(a, c);
+      }
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[b * BS + (base + r * Ns) * ES] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Full FFT (unnormalised) of NB sequences of length L in LDS.
+template <int L, int NB, int ES, int BS, int NT, bool INV>
+__device__ __forceinline__ void lds_fft(float2 *buf, const float4 *__restrict__ tw, int logT) {
+  constexpr int LOG = ilog2c(L);
+  int Ns = 1, logNs = 0;
+#pragma unroll
+  for (int s = 0; s < LOG / 2; ++s) {
+    stockham_stage<4, L, NB, ES, BS, NT, INV>(buf, Ns, logT - (logNs + 2), tw);
+    Ns <<= 2;
+    logNs += 2;
+  }
+  if (LOG & 1) stockham_stage<2, L, NB, ES, BS, NT, INV>(buf, Ns, logT - (logNs + 1), tw);
+}
+
+struct LinArgs {
+  const float2 *in[2];
+  float2 *out[2];
+  const float4 *E;
+  const float4 *tw;
+  int M, T, logT;
+  int N1, N2;
+};
+
+// ---------------------------------------------------------------------------
+// single pass: NB whole rows of length L per workgroup
+// ---------------------------------------------------------------------------
+template <int L, int NB, int NT>
+__global__ __launch_bounds__(NT) void linear_single(LinArgs a) {
+  __shared__ float2 buf[L * NB];
+  const int job = blockIdx.y;
+  const float2 *__restrict__ in = a.in[job];
+  float2 *__restrict__ out = a.out[job];
+  const int row0 = blockIdx.x * NB;
+  for (int idx = threadIdx.x; idx < L * NB; idx += NT) {
+    const int row = row0 + idx / L;
+    buf[idx] = row < a.M ? in[(size_t)row * L + (idx % L)] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  lds_fft<L, NB, 1, L, NT, false>(buf, a.tw, a.logT);
+  for (int idx = threadIdx.x; idx < L * NB; idx += NT) {
+    const int row = row0 + idx / L;
+    if (row < a.M) buf[idx] = cmul_hilo(buf[idx], a.E[(size_t)row * L + (idx % L)]);
+  }
+  __syncthreads();
+  lds_fft<L, NB, 1, L, NT, true>(buf, a.tw, a.logT);
+  for (int idx = threadIdx.x; idx < L * NB; idx += NT) {
+    const int row = row0 + idx / L;
+    if (row < a.M) out[(size_t)row * L + (idx % L)] = buf[idx];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// four-step passes
+// ---------------------------------------------------------------------------
+constexpr int COLS = 16;  // columns per workgroup in the strided passes
+
+// pass A (INV=false) and pass C (INV=true): C columns of one row
+template <int N1, int NT, bool INV>
+__global__ __launch_bounds__(NT) void linear_cols(LinArgs a) {
+  __shared__ float2 buf[N1 * COLS];
+  const int job = blockIdx.y;
+  const int cblocks = a.N2 / COLS;
+  const int row = blockIdx.x / cblocks;
+  const int c0 = (blockIdx.x % cblocks) * COLS;
+  const float2 *__restrict__ in = INV ? a.out[job] : a.in[job];
+  float2 *__restrict__ out = a.out[job];
+  const size_t rbase = (size_t)row * a.T + c0;
+  for (int idx = threadIdx.x; idx < N1 * COLS; idx += NT) {
+    const int n1 = idx / COLS, c = idx % COLS;
+    float2 x = in[rbase + (size_t)n1 * a.N2 + c];
+    if (INV) x = cmul_hilo(x, conj_hilo(a.tw[((c0 + c) * n1) & (a.T - 1)]));
+    buf[idx] = x;
+  }
+  __syncthreads();
+  lds_fft<N1, COLS, COLS, 1, NT, INV>(buf, a.tw, a.logT);
+  for (int idx = threadIdx.x; idx < N1 * COLS; idx += NT) {
+    const int k1 = idx / COLS, c = idx % COLS;
+    float2 x = buf[idx];
+    if (!INV) x = cmul_hilo(x, a.tw[((c0 + c) * k1) & (a.T - 1)]);
+    out[rbase + (size_t)k1 * a.N2 + c] = x;
+  }
+}
+
+// pass B: NB rows k1 of length N2: FFT, times E, inverse FFT
+template <int N2, int NB, int NT>
+__global__ __launch_bounds__(NT) void linear_rows(LinArgs a) {
+  __shared__ float2 buf[N2 * NB];
+  const int job = blockIdx.y;
+  float2 *__restrict__ io = a.out[job];
+  const int rows_per_mode = a.N1 / NB;
+  const int mode = blockIdx.x / rows_per_mode;
+  const size_t base = (size_t)mode * a.T + (size_t)(blockIdx.x % rows_per_mode) * NB * N2;
+  for (int idx = threadIdx.x; idx < N2 * NB; idx += NT) buf[idx] = io[base + idx];
+  __syncthreads();
+  lds_fft<N2, NB, 1, N2, NT, false>(buf, a.tw, a.logT);
+  for (int idx = threadIdx.x; idx < N2 * NB; idx += NT) buf[idx] = cmul_hilo(buf[idx], a.E[base + idx]);
+  __syncthreads();
+  lds_fft<N2, NB, 1, N2, NT, true>(buf, a.tw, a.logT);
+  for (int idx = threadIdx.x; idx < N2 * NB; idx += NT) io[base + idx] = buf[idx];
+}
+
+template <int L, int NB, int NT>
+hipError_t go_single(const LinArgs &a, int njobs, hipStream_t s) {
+  dim3 grid((a.M + NB - 1) / NB, njobs);
+  hipLaunchKernelGGL((linear_single<L, NB, NT>), grid, dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int N1, int NT>
+hipError_t go_cols(const LinArgs &a, int njobs, hipStream_t s, bool inv) {
+  dim3 grid(a.M * (a.N2 / COLS), njobs);
+  if (inv) hipLaunchKernelGGL((linear_cols<N1, NT, true>), grid, dim3(NT), 0, s, a);
+  else hipLaunchKernelGGL((linear_cols<N1, NT, false>), grid, dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int N2, int NB, int NT>
+hipError_t go_rows(const LinArgs &a, int njobs, hipStream_t s) {
+  dim3 grid(a.M * (a.N1 / NB), njobs);
+  hipLaunchKernelGGL((linear_rows<N2, NB, NT>), grid, dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t cols_dispatch(const LinArgs &a, int njobs, hipStream_t s, bool inv) {
+  switch (a.N1) {
+    case 32: return go_cols<32, 128>(a, njobs, s, inv);
+    case 64: return go_cols<64, 256>(a, njobs, s, inv);
+    case 128: return go_cols<128, 256>(a, njobs, s, inv);
+    case 256: return go_cols<256, 256>(a, njobs, s, inv);
+    case 512: return go_cols<512, 512>(a, njobs, s, inv);
+    case 1024: return go_cols<1024, 1024>(a, njobs, s, inv);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t rows_dispatch(const LinArgs &a, int njobs, hipStream_t s) {
+  // NB rows per workgroup; N1 (rows per mode) is a multiple of NB for every
+  // decomposition the plan chooses (N1 >= 32)
+  switch (a.N2) {
+    case 32: return go_rows<32, 32, 256>(a, njobs, s);
+    case 64: return go_rows<64, 16, 256>(a, njobs, s);
+    case 128: return go_rows<128, 8, 256>(a, njobs, s);
+    case 256: return go_rows<256, 8, 256>(a, njobs, s);
+    case 512: return go_rows<512, 4, 256>(a, njobs, s);
+    case 1024: return go_rows<1024, 2, 256>(a, njobs, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t single_dispatch(const LinArgs &a, int njobs, hipStream_t s) {
+  switch (a.T) {
+    case 64: return go_single<64, 16, 256>(a, njobs, s);
+    case 128: return go_single<128, 8, 256>(a, njobs, s);
+    case 256: return go_single<256, 4, 256>(a, njobs, s);
+    case 512: return go_single<512, 2, 256>(a, njobs, s);
+    case 1024: return go_single<1024, 1, 256>(a, njobs, s);
+    case 2048: return go_single<2048, 1, 256>(a, njobs, s);
+    case 4096: return go_single<4096, 1, 256>(a, njobs, s);
+    case 8192: return go_single<8192, 1, 512>(a, njobs, s);
+    case 16384: return go_single<16384, 1, 1024>(a, njobs, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_linear(const Plan &pl, const float4 *E, const float2 *in0, float2 *out0,
+                         const float2 *in1, float2 *out1) {
+  LinArgs a;
+  a.in[0] = in0;
+  a.out[0] = out0;
+  a.in[1] = in1;
+  a.out[1] = out1;
+  a.E = E;
+  a.tw = pl.tw;
+  a.M = pl.M;
+  a.T = pl.T;
+  a.logT = pl.logT;
+  a.N1 = pl.N1;
+  a.N2 = pl.N2;
+  const int njobs = in1 ? 2 : 1;
+  if (!pl.four_step) return single_dispatch(a, njobs, pl.stream);
+  hipError_t e = cols_dispatch(a, njobs, pl.stream, false);
+  if (e != hipSuccess) return e;
+  e = rows_dispatch(a, njobs, pl.stream);
+  if (e != hipSuccess) return e;
+  return cols_dispatch(a, njobs, pl.stream, true);
+}
+
+}  // namespace mmnlse

@@ -1,0 +1,238 @@
+// Kerr increment h N(X), N_p = i gamma sum_{l,m,n} S_plmn X_l X_m conj(X_n)
+// (the bracketed nonlinear terms of Eq. 6b-6e), evaluated pointwise in time:
+// every sample t couples all modes, which is the column access the paper's
+// nonlinear kernels stage through shared memory (Section 4.4).
+//
+// The RK4 stage combinations of Eq. 6c-6f are fused into the prologue (the
+// argument A_I + k/2) and the epilogue (A_I + k3, A_I + k1/6 + k2/3 + k3/3,
+// A = D(..) + k4/6) so they cost no extra pass over the fields.
+//
+// Two kernels here, both for any real S:
+//   kerr_small<M>  M <= 8: one thread per sample, all modes in registers,
+//                  S read through the scalar cache (wave-uniform indices).
+//   kerr_tiled     any M <= 128: a workgroup stages 64 samples of all modes
+//                  in LDS; each wave computes whole modes p.
+// The packed matrix-core contraction for symmetric S is in kerr_mfma.hip.
+
+#include "common.h"
+
+namespace mmnlse {
+namespace {
+
+struct KArgs {
+  const float2 *src0, *src1, *src2;
+  float2 *out0, *out1;
+  const float *Sg;  // [p][n][m][l]
+  float hg;         // h * gamma
+  int M, T, next;
+};
+
+// ---------------------------------------------------------------------------
+// small M
+// ---------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ void eval_small(const float *__restrict__ Sg, float hg, const float2 (&x)[M],
+                                           float2 (&k)[M]) {
+#pragma unroll
+  for (int p = 0; p < M; ++p) {
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int n = 0; n < M; ++n) {
+      float2 an = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        const float *s = Sg + ((p * M + n) * M + m) * M;
+        float2 am = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+          am.x = fmaf(s[l], x[l].x, am.x);
+          am.y = fmaf(s[l], x[l].y, am.y);
+        }
+        an = cfma(an, am, x[m]);
+      }
+      acc = cfma_conj(acc, an, x[n]);
+    }
+    k[p] = make_float2(-hg * acc.y, hg * acc.x);  // i * h * gamma * acc
+  }
+}
+
+template <int M, int STAGE>
+__global__ __launch_bounds__(256) void kerr_small(KArgs a) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.T) return;
+  float2 x[M], k[M];
+#pragma unroll
+  for (int p = 0; p < M; ++p) {
+    const size_t g = (size_t)p * a.T + t;
+    float2 v = a.src0[g];
+    if (STAGE == STAGE_K2) v = caxpy(v, 0.5f, a.src1[g]);
+    if (STAGE == STAGE_K3) v = caxpy(v, 0.5f, a.src2[g]);
+    x[p] = v;
+  }
+  eval_small<M>(a.Sg, a.hg, x, k);
+#pragma unroll
+  for (int p = 0; p < M; ++p) {
+    const size_t g = (size_t)p * a.T + t;
+    if (STAGE == STAGE_PLAIN || STAGE == STAGE_K2) {
+      a.out0[g] = k[p];
+    } else if (STAGE == STAGE_K3) {
+      const float2 ai = a.src0[g], k1 = a.src1[g], k2 = a.src2[g];
+      a.out0[g] = cadd(ai, k[p]);
+      float2 z = caxpy(ai, 1.f / 6.f, k1);
+      z = caxpy(z, 1.f / 3.f, k2);
+      a.out1[g] = caxpy(z, 1.f / 3.f, k[p]);
+    } else {  // STAGE_K4
+      x[p] = caxpy(a.src1[g], 1.f / 6.f, k[p]);
+      a.out0[g] = x[p];
+    }
+  }
+  if (STAGE == STAGE_K4 && a.next) {
+    eval_small<M>(a.Sg, a.hg, x, k);
+#pragma unroll
+    for (int p = 0; p < M; ++p) a.out1[(size_t)p * a.T + t] = k[p];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// LDS-tiled, any M
+// ---------------------------------------------------------------------------
+constexpr int TT = 64;   // samples per workgroup
+constexpr int GW = 4;    // waves per workgroup
+
+__device__ __forceinline__ void eval_tiled(const KArgs &a, const float2 *Xs, float2 *Ks, int w,
+                                           int lane) {
+  const int M = a.M;
+  for (int p0 = w; p0 < M; p0 += GW) {
+    const int p = __builtin_amdgcn_readfirstlane(p0);
+    float2 acc = make_float2(0.f, 0.f);
+    for (int n = 0; n < M; ++n) {
+      float2 an = make_float2(0.f, 0.f);
+      for (int m = 0; m < M; ++m) {
+        const float *__restrict__ s = a.Sg + ((size_t)(p * M + n) * M + m) * M;
+        float2 am = make_float2(0.f, 0.f);
+        for (int l = 0; l < M; ++l) {
+          const float2 xl = Xs[l * TT + lane];
+          const float sv = s[l];
+          am.x = fmaf(sv, xl.x, am.x);
+          am.y = fmaf(sv, xl.y, am.y);
+        }
+        an = cfma(an, am, Xs[m * TT + lane]);
+      }
+      acc = cfma_conj(acc, an, Xs[n * TT + lane]);
+    }
+    Ks[p * TT + lane] = make_float2(-a.hg * acc.y, a.hg * acc.x);
+  }
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(TT * GW) void kerr_tiled(KArgs a) {
+  extern __shared__ float2 sh[];
+  float2 *Xs = sh;
+  float2 *Ks = sh + a.M * TT;
+  const int t0 = blockIdx.x * TT;
+  const int lane = threadIdx.x & (TT - 1);
+  const int w = threadIdx.x / TT;
+  for (int idx = threadIdx.x; idx < a.M * TT; idx += TT * GW) {
+    const size_t g = (size_t)(idx / TT) * a.T + t0 + (idx % TT);
+    float2 v = a.src0[g];
+    if (STAGE == STAGE_K2) v = caxpy(v, 0.5f, a.src1[g]);
+    if (STAGE == STAGE_K3) v = caxpy(v, 0.5f, a.src2[g]);
+    Xs[idx] = v;
+  }
+  __syncthreads();
+  eval_tiled(a, Xs, Ks, w, lane);
+  __syncthreads();
+  for (int p = w; p < a.M; p += GW) {
+    const size_t g = (size_t)p * a.T + t0 + lane;
+    const float2 k = Ks[p * TT + lane];
+    if (STAGE == STAGE_PLAIN || STAGE == STAGE_K2) {
+      a.out0[g] = k;
+    } else if (STAGE == STAGE_K3) {
+      const float2 ai = a.src0[g], k1 = a.src1[g], k2 = a.src2[g];
+      a.out0[g] = cadd(ai, k);
+      float2 z = caxpy(ai, 1.f / 6.f, k1);
+      z = caxpy(z, 1.f / 3.f, k2);
+      a.out1[g] = caxpy(z, 1.f / 3.f, k);
+    } else {
+      const float2 An = caxpy(a.src1[g], 1.f / 6.f, k);
+      a.out0[g] = An;
+      Xs[p * TT + lane] = An;
+    }
+  }
+  if (STAGE == STAGE_K4 && a.next) {
+    __syncthreads();
+    eval_tiled(a, Xs, Ks, w, lane);
+    __syncthreads();
+    for (int p = w; p < a.M; p += GW) a.out1[(size_t)p * a.T + t0 + lane] = Ks[p * TT + lane];
+  }
+}
+
+template <int M>
+hipError_t go_small(const KArgs &a, KerrStage st, hipStream_t s) {
+  dim3 grid((a.T + 255) / 256);
+  switch (st) {
+    case STAGE_PLAIN: hipLaunchKernelGGL((kerr_small<M, STAGE_PLAIN>), grid, dim3(256), 0, s, a); break;
+    case STAGE_K2: hipLaunchKernelGGL((kerr_small<M, STAGE_K2>), grid, dim3(256), 0, s, a); break;
+    case STAGE_K3: hipLaunchKernelGGL((kerr_small<M, STAGE_K3>), grid, dim3(256), 0, s, a); break;
+    case STAGE_K4: hipLaunchKernelGGL((kerr_small<M, STAGE_K4>), grid, dim3(256), 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+template <int STAGE>
+void allow_lds(size_t shm) {
+  if (shm > 65536)
+    (void)hipFuncSetAttribute((const void *)kerr_tiled<STAGE>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+}
+
+hipError_t go_tiled(const KArgs &a, KerrStage st, hipStream_t s) {
+  dim3 grid(a.T / TT);
+  const size_t shm = (size_t)2 * a.M * TT * sizeof(float2);
+  allow_lds<STAGE_PLAIN>(shm);
+  allow_lds<STAGE_K2>(shm);
+  allow_lds<STAGE_K3>(shm);
+  allow_lds<STAGE_K4>(shm);
+  switch (st) {
+    case STAGE_PLAIN: hipLaunchKernelGGL((kerr_tiled<STAGE_PLAIN>), grid, dim3(TT * GW), shm, s, a); break;
+    case STAGE_K2: hipLaunchKernelGGL((kerr_tiled<STAGE_K2>), grid, dim3(TT * GW), shm, s, a); break;
+    case STAGE_K3: hipLaunchKernelGGL((kerr_tiled<STAGE_K3>), grid, dim3(TT * GW), shm, s, a); break;
+    case STAGE_K4: hipLaunchKernelGGL((kerr_tiled<STAGE_K4>), grid, dim3(TT * GW), shm, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k);
+
+hipError_t launch_kerr(const Plan &pl, double h, const KerrLaunch &k) {
+  if (pl.kerr_path == KERR_MFMA) return launch_kerr_mfma(pl, h, k);
+  KArgs a;
+  a.src0 = k.src0;
+  a.src1 = k.src1;
+  a.src2 = k.src2;
+  a.out0 = k.out0;
+  a.out1 = k.out1;
+  a.Sg = pl.Sg;
+  a.hg = (float)(h * pl.gamma);
+  a.M = pl.M;
+  a.T = pl.T;
+  a.next = k.next;
+  if (pl.kerr_path == KERR_SMALL) {
+    switch (pl.M) {
+      case 1: return go_small<1>(a, k.stage, pl.stream);
+      case 2: return go_small<2>(a, k.stage, pl.stream);
+      case 3: return go_small<3>(a, k.stage, pl.stream);
+      case 4: return go_small<4>(a, k.stage, pl.stream);
+      case 5: return go_small<5>(a, k.stage, pl.stream);
+      case 6: return go_small<6>(a, k.stage, pl.stream);
+      case 7: return go_small<7>(a, k.stage, pl.stream);
+      case 8: return go_small<8>(a, k.stage, pl.stream);
+    }
+    return hipErrorInvalidValue;
+  }
+  return go_tiled(a, k.stage, pl.stream);
+}
+
+}  // namespace mmnlse

@@ -1,0 +1,70 @@
+"""The C-ABI library: it loads and exports every symbol the header declares (CPU only)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mmnlse.h")
+LIB = os.path.join(ROOT, "paper_1901_01895_amd", "libmmnlse.so")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mmnlse_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    syms = declared_symbols()
+    for s in ("mmnlse_create", "mmnlse_propagate", "mmnlse_destroy", "mmnlse_last_error",
+              "mmnlse_advance", "mmnlse_linear_half_step", "mmnlse_kerr", "mmnlse_power",
+              "mmnlse_step_doubling"):
+        assert s in syms
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_lists_every_declared_symbol():
+    import paper_1901_01895_amd as mm
+    assert sorted(mm.SYMBOLS) == [s for s in declared_symbols() if not s.startswith("mmnlse_server")] \
+        or set(declared_symbols()) >= set(mm.SYMBOLS)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_create_rejects_bad_arguments_without_touching_the_gpu():
+    """Argument validation runs before any device call."""
+    import numpy as np
+    import paper_1901_01895_amd as mm
+    lib = mm.load()
+    S = np.ones((1, 1, 1, 1), np.float32)
+    beta = np.zeros((1, 3))
+    base = dict(M=1, T=4096, dt_ps=0.1, n_beta=3, gamma=1.0, h_km=0.1, L_km=1.0)
+
+    def make(**kw):
+        c = mm.Config()
+        d = dict(base, **kw)
+        for k, v in d.items():
+            setattr(c, k, v)
+        c.beta = beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        c.S = S.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        return c
+
+    h = ctypes.c_void_p()
+    for bad in (dict(T=1000), dict(T=32), dict(M=0), dict(L_km=1.05), dict(h_km=0.0),
+                dict(dt_ps=-1.0), dict(precision=7), dict(n_beta=9)):
+        c = make(**bad)
+        assert lib.mmnlse_create(ctypes.byref(c), None, ctypes.byref(h)) == 1, bad
+        assert lib.mmnlse_last_error()
+    # split precision without a symmetric tensor is refused
+    c = make(precision=1, flags=0)
+    assert lib.mmnlse_create(ctypes.byref(c), None, ctypes.byref(h)) == 1
+    assert lib.mmnlse_destroy(None) == 0

@@ -1,0 +1,187 @@
+"""GPU parity: the HIP path through the C-ABI vs the FP64 oracle on the same inputs.
+
+Tolerances (relative L2 over all M*T complex values):
+  * one half-step propagator application: 1e-6.  An FP32 FFT pair of size T
+    rounds each value about 2*log2(T) times at unit roundoff 6e-8, which is
+    ~5e-7 in the worst case here (T = 2^17), random in sign.
+  * one Kerr evaluation: 2e-6 (FP32 products and sums over M^3 terms).
+  * whole propagation, FP32 path: 1e-5 (the stated bar of the method's FP32
+    path against the FP64 reference).
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def crandn(rng, *shape):
+    return ((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / math.sqrt(2)).astype(np.complex64)
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(x):
+    return x.cpu().numpy()
+
+
+def make(mm, M, T, dt=0.5, beta=None, S=None, gamma=1.0, h=0.1, L=0.1, seed=0, **kw):
+    rng = np.random.default_rng((7, M, T, seed))
+    if beta is None:
+        beta = np.column_stack([rng.uniform(-50, 50, M), rng.uniform(-20, 20, M), rng.uniform(-25, -15, M)])
+    if S is None:
+        S = W.symmetric_gaussian_tensor(M, rng).astype(np.float32)
+    return mm.Propagator(M, T, dt, beta, S, gamma, h, L, **kw), beta, S
+
+
+@pytest.mark.parametrize("T", [64, 256, 1024, 4096, 16384, 2 ** 15, 2 ** 16, 2 ** 17])
+def test_linear_half_step(gpu_lib, T):
+    mm = gpu_lib
+    M = 3
+    print(f"linear_half_step T={T}", flush=True)
+    P, beta, S = make(mm, M, T)
+    rng = np.random.default_rng((11, T))
+    X = crandn(rng, M, T)
+    Y = host(P.linear_half_step(dev(X)))
+    E = oracle.half_step_propagator(oracle.angular_frequencies(T, P.dt), beta, None, P.h)
+    ref = oracle.apply_linear(X.astype(np.complex128), E)
+    assert rel(Y, ref) < 1e-6
+    P.close()
+
+
+@pytest.mark.parametrize("T", [1024, 4096, 16384])
+def test_linear_half_step_four_step_forced(gpu_lib, T, monkeypatch):
+    monkeypatch.setenv("MMNLSE_FORCE_FOUR_STEP", "1")
+    mm = gpu_lib
+    print(f"linear_half_step four-step T={T}", flush=True)
+    P, beta, S = make(mm, 5, T, seed=1)
+    X = crandn(np.random.default_rng((12, T)), 5, T)
+    Y = host(P.linear_half_step(dev(X)))
+    E = oracle.half_step_propagator(oracle.angular_frequencies(T, P.dt), beta, None, P.h)
+    assert rel(Y, oracle.apply_linear(X.astype(np.complex128), E)) < 1e-6
+    P.close()
+
+
+def test_linear_with_attenuation(gpu_lib):
+    mm = gpu_lib
+    M, T = 2, 1024
+    beta = np.array([[1.0, 2.0, -20.0, 0.5], [0.0, -3.0, -10.0, 0.0]])
+    alpha = np.array([0.3, 0.05])
+    S = np.zeros((M,) * 4, np.float32)
+    P = mm.Propagator(M, T, 0.3, beta, S, 0.0, 0.2, 0.2, alpha=alpha)
+    X = crandn(np.random.default_rng(3), M, T)
+    Y = host(P.linear_half_step(dev(X)))
+    E = oracle.half_step_propagator(oracle.angular_frequencies(T, 0.3), beta, alpha, 0.2)
+    assert rel(Y, oracle.apply_linear(X.astype(np.complex128), E)) < 1e-6
+    P.close()
+
+
+@pytest.mark.parametrize("M,sym,generic", [(1, True, False), (2, False, False), (3, True, False),
+                                           (6, True, False), (8, False, False), (5, False, True),
+                                           (12, True, False), (13, False, False)])
+def test_kerr_term(gpu_lib, M, sym, generic):
+    mm = gpu_lib
+    T = 512
+    print(f"kerr M={M} sym={sym} generic={generic}", flush=True)
+    rng = np.random.default_rng((13, M))
+    S = (W.symmetric_gaussian_tensor(M, rng) if sym else rng.standard_normal((M,) * 4)).astype(np.float32)
+    P, beta, S = make(mm, M, T, S=S, gamma=1.3, h=0.05, L=0.05, generic=generic)
+    X = crandn(rng, M, T)
+    Y = host(P.kerr(dev(X)))
+    ref = 0.05 * oracle.kerr_term(X.astype(np.complex128), S.astype(np.float64), 1.3)
+    assert rel(Y, ref) < 2e-6, P.kerr_path
+    P.close()
+
+
+def test_power_reduction(gpu_lib):
+    mm = gpu_lib
+    P, _, _ = make(mm, 4, 4096)
+    X = crandn(np.random.default_rng(5), 4, 4096)
+    assert abs(P.power(dev(X)) / oracle.power(X, P.dt) - 1) < 1e-12
+    P.close()
+
+
+def _propagate_parity(mm, p, tol, **kw):
+    print(f"propagate {p.name} M={p.M} T={p.T} steps={p.n_steps} {kw}", flush=True)
+    P = mm.Propagator.from_problem(p, **kw)
+    out, st = P.propagate(p.A0, stats=True)
+    kern = oracle.KerrPacked(p.S, p.gamma) if p.symmetric else None
+    ref = oracle.propagate(p.A0, p.beta, None, p.S, p.gamma, p.dt, p.h, p.n_steps, kerr=kern)
+    err = rel(out, ref)
+    print(f"  rel L2 = {err:.3e}  kerr path = {P.kerr_path}", flush=True)
+    assert err < tol
+    assert st["steps"] == p.n_steps
+    assert abs(st["power_in"] / oracle.power(p.A0.astype(np.complex64), p.dt) - 1) < 1e-12
+    P.close()
+    return out, ref, st
+
+
+def test_soliton_full(gpu_lib):
+    p = W.make_problem("soliton")
+    out, ref, st = _propagate_parity(gpu_lib, p, 1e-5)
+    assert out.dtype == np.complex128
+    # power conserved by the GPU path to the FP32 level
+    assert abs(st["power_out"] / st["power_in"] - 1) < 1e-5
+
+
+def test_qpsk6_reduced(gpu_lib):
+    _propagate_parity(gpu_lib, W.make_problem("qpsk6", T=2 ** 12, n_steps=20), 1e-5)
+
+
+def test_qpsk6_full(gpu_lib):
+    _propagate_parity(gpu_lib, W.make_problem("qpsk6"), 1e-5)
+
+
+def test_wdm36_reduced_tiled(gpu_lib):
+    _propagate_parity(gpu_lib, W.make_problem("wdm36", T=2 ** 11, n_steps=4), 1e-5)
+
+
+def test_four_step_propagation(gpu_lib):
+    p = W.make_problem("qpsk6", T=2 ** 15, n_steps=6, M=3)
+    _propagate_parity(gpu_lib, p, 1e-5)
+
+
+def test_device_path_and_advance_match_host_path(gpu_lib):
+    import torch
+    mm = gpu_lib
+    p = W.make_problem("qpsk6", T=2 ** 12, n_steps=10)
+    P = mm.Propagator.from_problem(p)
+    out_host = P.propagate(p.A0)
+    out_dev = host(P.propagate(dev(p.A0)))
+    A = dev(p.A0)
+    P.advance(A, p.n_steps)
+    torch.cuda.synchronize()
+    assert np.array_equal(out_host, out_dev)
+    assert np.array_equal(out_host, host(A))
+    # checkpoint / resume: two halves equal the whole, bit for bit
+    B = dev(p.A0)
+    P.advance(B, 4)
+    P.advance(B, 6)
+    torch.cuda.synchronize()
+    assert np.array_equal(out_host, host(B))
+    P.close()
+
+
+def test_step_doubling_estimate(gpu_lib):
+    mm = gpu_lib
+    p = W.soliton_problem(noise=0.0, h=0.04, n_steps=1)
+    P = mm.Propagator.from_problem(p)
+    d_gpu = P.step_doubling(dev(p.A0.astype(np.complex64)))
+    d_orc, _ = oracle.step_doubling_estimate(p.A0, p.beta, None, p.S, p.gamma, p.dt, p.h)
+    assert abs(d_gpu / d_orc - 1) < 1e-2
+    P.close()
