@@ -278,6 +278,7 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
   if (cfg->precision == MMNLSE_SPLIT_BF16) pl->kerr_path = KERR_MFMA;
   else if (force_generic) pl->kerr_path = KERR_GENERIC;
   else if (M <= 8) pl->kerr_path = KERR_SMALL;
+  else if (sym) pl->kerr_path = KERR_MFMA;
   else pl->kerr_path = KERR_GENERIC;
   if (fpath && !force_generic && cfg->precision == MMNLSE_FP32) {
     const int v = std::atoi(fpath);

@@ -1,13 +1,338 @@
-// Packed symmetric Kerr contraction on matrix cores (placeholder until the
-// MFMA kernel lands; the plan never selects this path yet).
+// Packed Kerr contraction on matrix cores for a tensor symmetric in (l,m)
+// and in (p,n) (every fully symmetric tensor).
+//
+// With pairs q = (l <= m) and r = (p <= n), P = M(M+1)/2 of each,
+//   B_q(t)  = X_l(t) X_m(t)                              (formed on the fly)
+//   C_r(t)  = sum_q Sp[r][q] B_q(t),  Sp[r][q] = w_q S[p,l,m,n], w_q = 2 for l<m
+//   N_p(t)  = i gamma ( sum_{r=(p,n)} C_r conj(X_n) + sum_{r=(n,p), n<p} C_r conj(X_n) ),
+// i.e. one real GEMM Sp[P x P] * [Re B | Im B][P x 2T] per evaluation plus a
+// cheap scatter; this is the dense part of the Kerr term and it runs on MFMA.
+//
+// Workgroup = W waves; wave w owns 32 samples (64 real GEMM columns: the real
+// and imaginary parts of B), so a workgroup covers 32W samples of every mode.
+// Every wave walks all row tiles of Sp (32 rows each, RT at a time so that
+// one B fragment feeds RT tiles); Sp is pre-swizzled so that each lane loads
+// its MFMA A-operand with one coalesced 16-byte load.  The mode-space
+// epilogue accumulates into the wave's own columns of an LDS tile, so no
+// atomics are needed and the result is deterministic.
+//
+// FP32 path: v_mfma_f32_32x32x2_f32.  Split path: Sp and B are split into
+// bf16 hi + lo (lo = bf16(x - hi)); hi*hi + hi*lo + lo*hi on
+// v_mfma_f32_32x32x16_bf16, accumulated in FP32 (the lo*lo term, 2^-16 of
+// the product, is dropped).
+
+#include <cstring>
+#include <vector>
+
 #include "common.h"
 
 namespace mmnlse {
+namespace {
 
-hipError_t launch_kerr_mfma(const Plan &, double, const KerrLaunch &) { return hipErrorNotSupported; }
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-hipError_t launch_pack_bf16(const Plan &) { return hipErrorNotSupported; }
+struct MArgs {
+  const float2 *src0, *src1, *src2;
+  float2 *out0, *out1;
+  const float4 *A32;     // FP32 swizzle: [Ppad/32][Ppad/8][64] float4
+  const uint4 *Ah, *Al;  // bf16 swizzle: [Ppad/32][Ppad/16][64] 8 x bf16
+  const int *pairs;      // [Ppad] a | b << 16 (padding rows/cols -> (0,0), zero weight)
+  float hg;
+  int M, T, P, Ppad, next;
+};
 
-hipError_t setup_mfma(Plan &, const float *) { return hipErrorNotSupported; }
+// Output row of accumulator register v for lane-half `half` of a 32x32 tile.
+__device__ __forceinline__ int acc_row(int v, int half) { return 8 * (v >> 2) + 4 * half + (v & 3); }
+
+template <int TT>
+__device__ __forceinline__ void scatter_tile(const MArgs &a, const floatx16 &cre, const floatx16 &cim,
+                                             int rt, const float2 *Xs, float2 *Os, int lane, int col) {
+  const int half = lane >> 5;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      // one lane-half at a time: its 32 lanes share the row, so the LDS
+      // read-modify-writes below touch 32 distinct samples
+      if (half == h) {
+        const int i = rt * 32 + acc_row(v, h);
+        if (i < a.P) {
+          const int ab = a.pairs[i];
+          const int p = ab & 0xffff, n = ab >> 16;
+          const float2 C = make_float2(cre[v], cim[v]);
+          Os[p * TT + col] = cfma_conj(Os[p * TT + col], C, Xs[n * TT + col]);
+          if (p != n) Os[n * TT + col] = cfma_conj(Os[n * TT + col], C, Xs[p * TT + col]);
+        }
+      }
+    }
+  }
+}
+
+// One full contraction for the wave's 32 samples: Os[:, cols] += sum over all rows.
+template <int W, int RT, bool SPLIT>
+__device__ __forceinline__ void contract(const MArgs &a, const float2 *Xs, float2 *Os, int lane, int col) {
+  constexpr int TT = 32 * W;
+  const int half = lane >> 5;
+  const int nrt = a.Ppad / 32;
+  for (int rt0 = 0; rt0 < nrt; rt0 += RT) {
+    floatx16 cre[RT], cim[RT];
+#pragma unroll
+    for (int j = 0; j < RT; ++j) {
+      cre[j] = floatx16{0};
+      cim[j] = floatx16{0};
+    }
+    if (!SPLIT) {
+      const int nk = a.Ppad / 8;  // 4 k-steps of 2 per iteration
+      for (int kq = 0; kq < nk; ++kq) {
+        float4 av[RT];
+#pragma unroll
+        for (int j = 0; j < RT; ++j) av[j] = a.A32[((size_t)(rt0 + j) * nk + kq) * 64 + lane];
+        const int4 p0 = *(const int4 *)(a.pairs + 8 * kq);
+        const int4 p1 = *(const int4 *)(a.pairs + 8 * kq + 4);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int lo = s == 0 ? p0.x : s == 1 ? p0.z : s == 2 ? p1.x : p1.z;
+          const int hi = s == 0 ? p0.y : s == 1 ? p0.w : s == 2 ? p1.y : p1.w;
+          const int ab = half ? hi : lo;
+          const float2 xa = Xs[(ab & 0xffff) * TT + col];
+          const float2 xb = Xs[(ab >> 16) * TT + col];
+          const float bre = fmaf(xa.x, xb.x, -xa.y * xb.y);
+          const float bim = fmaf(xa.x, xb.y, xa.y * xb.x);
+#pragma unroll
+          for (int j = 0; j < RT; ++j) {
+            const float av_s = s == 0 ? av[j].x : s == 1 ? av[j].y : s == 2 ? av[j].z : av[j].w;
+            cre[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, bre, cre[j], 0, 0, 0);
+            cim[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, bim, cim[j], 0, 0, 0);
+          }
+        }
+      }
+    } else {
+      const int nk = a.Ppad / 16;  // k-steps of 16
+      for (int ks = 0; ks < nk; ++ks) {
+        uint4 ah[RT], al[RT];
+#pragma unroll
+        for (int j = 0; j < RT; ++j) {
+          ah[j] = a.Ah[((size_t)(rt0 + j) * nk + ks) * 64 + lane];
+          al[j] = a.Al[((size_t)(rt0 + j) * nk + ks) * 64 + lane];
+        }
+        const int *pp = a.pairs + 16 * ks + 8 * half;
+        bf16x8 rh, rl, ih, il;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int ab = pp[e];
+          const float2 xa = Xs[(ab & 0xffff) * TT + col];
+          const float2 xb = Xs[(ab >> 16) * TT + col];
+          const float bre = fmaf(xa.x, xb.x, -xa.y * xb.y);
+          const float bim = fmaf(xa.x, xb.y, xa.y * xb.x);
+          const __bf16 hr = (__bf16)bre, hi = (__bf16)bim;
+          rh[e] = hr;
+          ih[e] = hi;
+          rl[e] = (__bf16)(bre - (float)hr);
+          il[e] = (__bf16)(bim - (float)hi);
+        }
+#pragma unroll
+        for (int j = 0; j < RT; ++j) {
+          const bf16x8 sh = __builtin_bit_cast(bf16x8, ah[j]);
+          const bf16x8 sl = __builtin_bit_cast(bf16x8, al[j]);
+          cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, rh, cre[j], 0, 0, 0);
+          cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rl, cre[j], 0, 0, 0);
+          cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rh, cre[j], 0, 0, 0);
+          cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, ih, cim[j], 0, 0, 0);
+          cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, il, cim[j], 0, 0, 0);
+          cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, ih, cim[j], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < RT; ++j) scatter_tile<TT>(a, cre[j], cim[j], rt0 + j, Xs, Os, lane, col);
+  }
+}
+
+template <int W, int RT, bool SPLIT, int STAGE>
+__global__ __launch_bounds__(64 * W) void kerr_mfma(MArgs a) {
+  constexpr int TT = 32 * W;
+  constexpr int NT = 64 * W;
+  extern __shared__ float2 sh[];
+  float2 *Xs = sh;
+  float2 *Os = sh + a.M * TT;
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int col = 32 * w + (lane & 31);
+  const int t0 = blockIdx.x * TT;
+  for (int idx = threadIdx.x; idx < a.M * TT; idx += NT) {
+    const size_t g = (size_t)(idx / TT) * a.T + t0 + (idx % TT);
+    float2 v = a.src0[g];
+    if (STAGE == STAGE_K2) v = caxpy(v, 0.5f, a.src1[g]);
+    if (STAGE == STAGE_K3) v = caxpy(v, 0.5f, a.src2[g]);
+    Xs[idx] = v;
+    Os[idx] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  contract<W, RT, SPLIT>(a, Xs, Os, lane, col);
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < a.M * TT; idx += NT) {
+    const size_t g = (size_t)(idx / TT) * a.T + t0 + (idx % TT);
+    const float2 o = Os[idx];
+    const float2 k = make_float2(-a.hg * o.y, a.hg * o.x);  // i h gamma sum
+    if (STAGE == STAGE_PLAIN || STAGE == STAGE_K2) {
+      a.out0[g] = k;
+    } else if (STAGE == STAGE_K3) {
+      const float2 ai = a.src0[g], k1 = a.src1[g], k2 = a.src2[g];
+      a.out0[g] = cadd(ai, k);
+      float2 z = caxpy(ai, 1.f / 6.f, k1);
+      z = caxpy(z, 1.f / 3.f, k2);
+      a.out1[g] = caxpy(z, 1.f / 3.f, k);
+    } else {
+      const float2 An = caxpy(a.src1[g], 1.f / 6.f, k);
+      a.out0[g] = An;
+      Xs[idx] = An;
+      Os[idx] = make_float2(0.f, 0.f);
+    }
+  }
+  if (STAGE == STAGE_K4 && a.next) {
+    __syncthreads();
+    contract<W, RT, SPLIT>(a, Xs, Os, lane, col);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < a.M * TT; idx += NT) {
+      const float2 o = Os[idx];
+      a.out1[(size_t)(idx / TT) * a.T + t0 + (idx % TT)] = make_float2(-a.hg * o.y, a.hg * o.x);
+    }
+  }
+}
+
+constexpr int RT_F32 = 2;
+constexpr int RT_BF16 = 2;
+
+template <int W, int RT, bool SPLIT>
+hipError_t go(const MArgs &a, KerrStage st, hipStream_t s) {
+  constexpr int TT = 32 * W;
+  const dim3 grid(a.T / TT), block(64 * W);
+  const size_t shm = (size_t)2 * a.M * TT * sizeof(float2);
+  auto launch = [&](auto kern) -> hipError_t {
+    if (shm > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, grid, block, shm, s, a);
+    return hipGetLastError();
+  };
+  switch (st) {
+    case STAGE_PLAIN: return launch(kerr_mfma<W, RT, SPLIT, STAGE_PLAIN>);
+    case STAGE_K2: return launch(kerr_mfma<W, RT, SPLIT, STAGE_K2>);
+    case STAGE_K3: return launch(kerr_mfma<W, RT, SPLIT, STAGE_K3>);
+    case STAGE_K4: return launch(kerr_mfma<W, RT, SPLIT, STAGE_K4>);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <bool SPLIT>
+hipError_t go_w(const MArgs &a, KerrStage st, hipStream_t s) {
+  constexpr int RT = SPLIT ? RT_BF16 : RT_F32;
+  if (a.M <= 64 && a.T % 128 == 0) return go<4, RT, SPLIT>(a, st, s);
+  if (a.M <= 128) return go<2, RT, SPLIT>(a, st, s);
+  return go<1, RT, SPLIT>(a, st, s);
+}
+
+uint16_t bf16_bits(float x) {  // round to nearest even
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  return (uint16_t)(u >> 16);
+}
+
+float bf16_value(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float x;
+  std::memcpy(&x, &u, 4);
+  return x;
+}
+
+}  // namespace
+
+hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k) {
+  MArgs a;
+  a.src0 = k.src0;
+  a.src1 = k.src1;
+  a.src2 = k.src2;
+  a.out0 = k.out0;
+  a.out1 = k.out1;
+  a.A32 = (const float4 *)pl.Sp;
+  a.Ah = (const uint4 *)pl.Sph;
+  a.Al = (const uint4 *)pl.Spl;
+  a.pairs = pl.pairs;
+  a.hg = (float)(h * pl.gamma);
+  a.M = pl.M;
+  a.T = pl.T;
+  a.P = pl.P;
+  a.Ppad = pl.Ppad;
+  a.next = k.next;
+  if (pl.precision == MMNLSE_SPLIT_BF16) return go_w<true>(a, k.stage, pl.stream);
+  return go_w<false>(a, k.stage, pl.stream);
+}
+
+hipError_t launch_pack_bf16(const Plan &) { return hipSuccess; }
+
+// Build the packed tensor, its pair table and the swizzled operand tables.
+hipError_t setup_mfma(Plan &pl, const float *S) {
+  const int M = pl.M;
+  const int P = M * (M + 1) / 2;
+  const int RT = pl.precision == MMNLSE_SPLIT_BF16 ? RT_BF16 : RT_F32;
+  const int quantum = 32 * RT;  // rows per pass; also a multiple of 16 for the bf16 k-steps
+  const int Ppad = ((P + quantum - 1) / quantum) * quantum;
+  pl.P = P;
+  pl.Ppad = Ppad;
+  std::vector<int> a(Ppad, 0), b(Ppad, 0);
+  std::vector<int32_t> pairs(Ppad, 0);
+  {
+    int r = 0;
+    for (int i = 0; i < M; ++i)
+      for (int j = i; j < M; ++j, ++r) {
+        a[r] = i;
+        b[r] = j;
+        pairs[r] = i | (j << 16);
+      }
+  }
+  // Sp[r][q] = w_q S[a_r, a_q, b_q, b_r]
+  auto Sp = [&](int r, int q) -> float {
+    if (r >= P || q >= P) return 0.f;
+    const float w = a[q] < b[q] ? 2.f : 1.f;
+    return w * S[(((size_t)a[r] * M + a[q]) * M + b[q]) * M + b[r]];
+  };
+  hipError_t e;
+  auto alloc_copy = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
+    hipError_t r = hipMalloc(dst, bytes);
+    if (r != hipSuccess) return r;
+    pl.bytes += bytes;
+    return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  if ((e = alloc_copy((void **)&pl.pairs, pairs.data(), sizeof(int32_t) * Ppad)) != hipSuccess) return e;
+  const int nrt = Ppad / 32;
+  if (pl.precision != MMNLSE_SPLIT_BF16) {
+    const int nk = Ppad / 8;
+    std::vector<float> sw((size_t)Ppad * Ppad);
+    for (int rt = 0; rt < nrt; ++rt)
+      for (int kq = 0; kq < nk; ++kq)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int s = 0; s < 4; ++s)
+            sw[(((size_t)rt * nk + kq) * 64 + lane) * 4 + s] = Sp(rt * 32 + (lane & 31), 8 * kq + 2 * s + (lane >> 5));
+    return alloc_copy((void **)&pl.Sp, sw.data(), sizeof(float) * sw.size());
+  }
+  const int nk = Ppad / 16;
+  std::vector<uint16_t> hi((size_t)Ppad * Ppad), lo((size_t)Ppad * Ppad);
+  for (int rt = 0; rt < nrt; ++rt)
+    for (int ks = 0; ks < nk; ++ks)
+      for (int lane = 0; lane < 64; ++lane)
+        for (int e8 = 0; e8 < 8; ++e8) {
+          const float v = Sp(rt * 32 + (lane & 31), 16 * ks + 8 * (lane >> 5) + e8);
+          const uint16_t hb = bf16_bits(v);
+          const size_t idx = (((size_t)rt * nk + ks) * 64 + lane) * 8 + e8;
+          hi[idx] = hb;
+          lo[idx] = bf16_bits(v - bf16_value(hb));
+        }
+  if ((e = alloc_copy((void **)&pl.Sph, hi.data(), sizeof(uint16_t) * hi.size())) != hipSuccess) return e;
+  return alloc_copy((void **)&pl.Spl, lo.data(), sizeof(uint16_t) * lo.size());
+}
 
 }  // namespace mmnlse

@@ -91,20 +91,42 @@ def test_linear_with_attenuation(gpu_lib):
     P.close()
 
 
-@pytest.mark.parametrize("M,sym,generic", [(1, True, False), (2, False, False), (3, True, False),
-                                           (6, True, False), (8, False, False), (5, False, True),
-                                           (12, True, False), (13, False, False)])
-def test_kerr_term(gpu_lib, M, sym, generic):
+@pytest.mark.parametrize("M,sym,generic,path", [
+    (1, True, False, "small"), (2, False, False, "small"), (3, True, False, "small"),
+    (6, True, False, "small"), (8, False, False, "small"), (5, False, True, "tiled"),
+    (12, True, True, "tiled"), (13, False, False, "tiled"),
+    (9, True, False, "mfma"), (12, True, False, "mfma"), (36, True, False, "mfma"),
+    (70, True, False, "mfma")])
+def test_kerr_term(gpu_lib, M, sym, generic, path):
     mm = gpu_lib
     T = 512
     print(f"kerr M={M} sym={sym} generic={generic}", flush=True)
     rng = np.random.default_rng((13, M))
     S = (W.symmetric_gaussian_tensor(M, rng) if sym else rng.standard_normal((M,) * 4)).astype(np.float32)
     P, beta, S = make(mm, M, T, S=S, gamma=1.3, h=0.05, L=0.05, generic=generic)
+    assert P.kerr_path == path
     X = crandn(rng, M, T)
     Y = host(P.kerr(dev(X)))
     ref = 0.05 * oracle.kerr_term(X.astype(np.complex128), S.astype(np.float64), 1.3)
     assert rel(Y, ref) < 2e-6, P.kerr_path
+    P.close()
+
+
+@pytest.mark.parametrize("M", [9, 36])
+def test_kerr_term_split_bf16(gpu_lib, M):
+    """Split-bf16 contraction: S and B = X_l X_m each carried as bf16 hi + lo, three
+    products accumulated in FP32; each product keeps ~16 significant bits, so one
+    evaluation lands within ~1e-5 of the FP64 value."""
+    mm = gpu_lib
+    T = 512
+    rng = np.random.default_rng((14, M))
+    S = W.symmetric_gaussian_tensor(M, rng).astype(np.float32)
+    P, beta, S = make(mm, M, T, S=S, gamma=1.3, h=0.05, L=0.05, precision=mm.SPLIT_BF16)
+    assert P.kerr_path == "mfma"
+    X = crandn(rng, M, T)
+    Y = host(P.kerr(dev(X)))
+    ref = 0.05 * oracle.kerr_term(X.astype(np.complex128), S.astype(np.float64), 1.3)
+    assert rel(Y, ref) < 3e-5
     P.close()
 
 
@@ -148,7 +170,17 @@ def test_qpsk6_full(gpu_lib):
 
 
 def test_wdm36_reduced_tiled(gpu_lib):
-    _propagate_parity(gpu_lib, W.make_problem("wdm36", T=2 ** 11, n_steps=4), 1e-5)
+    _propagate_parity(gpu_lib, W.make_problem("wdm36", T=2 ** 11, n_steps=4), 1e-5, generic=True)
+
+
+def test_wdm36_reduced_mfma(gpu_lib):
+    _propagate_parity(gpu_lib, W.make_problem("wdm36", T=2 ** 12, n_steps=20), 1e-5)
+
+
+def test_wdm36_reduced_split_bf16(gpu_lib):
+    import paper_1901_01895_amd as mm
+    _propagate_parity(gpu_lib, W.make_problem("wdm36", T=2 ** 12, n_steps=20), 1e-4,
+                      precision=mm.SPLIT_BF16)
 
 
 def test_four_step_propagation(gpu_lib):
