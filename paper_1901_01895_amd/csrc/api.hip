@@ -120,7 +120,7 @@ static void free_plan(Plan *pl) {
 //   K_4    k4 = h N(W0); A <- W1 + k4/6                  Eq. 6e, 6f
 //          and, unless last, W0 = h N(A) for the next step.
 hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float4 *E,
-                     float2 *const *work, Prof *prof) {
+                     float2 *const *work, Prof *prof, bool start, bool finish) {
   if (n_steps <= 0) return hipSuccess;
   float2 *W0 = work[0], *W1 = work[1];
   hipError_t e;
@@ -139,10 +139,12 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
     return prof ? prof->record(prof->lin, pl.stream) : hipSuccess;
   };
   KerrLaunch k{};
-  k.stage = STAGE_PLAIN;
-  k.src0 = A;
-  k.out0 = W0;
-  if ((e = kerr(k)) != hipSuccess) return e;
+  if (start) {
+    k.stage = STAGE_PLAIN;
+    k.src0 = A;
+    k.out0 = W0;
+    if ((e = kerr(k)) != hipSuccess) return e;
+  }
   for (int64_t s = 0; s < n_steps; ++s) {
     if ((e = linear(A, W0)) != hipSuccess) return e;
     k = KerrLaunch{};
@@ -166,7 +168,7 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
     k.src1 = W1;
     k.out0 = A;
     k.out1 = W0;
-    k.next = (s + 1 < n_steps) ? 1 : 0;
+    k.next = (s + 1 < n_steps || !finish) ? 1 : 0;
     if ((e = kerr(k)) != hipSuccess) return e;
   }
   return hipSuccess;
@@ -197,13 +199,24 @@ static bool check_symmetric(const float *S, int M, double tol, std::string &why)
 
 hipError_t setup_mfma(Plan &pl, const float *S);  // kerr_mfma.hip
 
+size_t estimate_plan_bytes(const mmnlse_config &cfg) {
+  const size_t M = (size_t)cfg.M, T = (size_t)cfg.T, MT = M * T;
+  size_t b = 3 * MT * sizeof(float2) + MT * sizeof(float4) + T * sizeof(float4) + 1024 * sizeof(double2);
+  const bool sym = (cfg.flags & MMNLSE_S_SYMMETRIC) != 0;
+  const bool mfma = cfg.precision == MMNLSE_SPLIT_BF16 ||
+                    (!(cfg.flags & MMNLSE_KERR_GENERIC) && cfg.M > 8 && sym);
+  if (mfma) {
+    const size_t P = M * (M + 1) / 2, Ppad = (P + 63) / 64 * 64;
+    b += Ppad * Ppad * 4 + Ppad * 4;  // FP32, or bf16 hi + lo: 4 bytes per entry either way
+  } else {
+    b += M * M * M * M * sizeof(float);
+  }
+  return b;
+}
+
 }  // namespace mmnlse
 
 using namespace mmnlse;
-
-struct mmnlse_ctx {
-  Plan *pl;
-};
 
 extern "C" {
 

@@ -135,8 +135,20 @@ struct Prof {
   }
 };
 
-// the RK4IP step schedule
+// The RK4IP step schedule.  work[0] carries h N(A) between steps: `start`
+// computes it from A first, `finish` leaves it out after the last step.  A
+// propagation split into chunks (first chunk start, last chunk finish, the
+// work buffers kept between chunks) does exactly the arithmetic of one call.
 hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float4 *E,
-                     float2 *const *work, Prof *prof = nullptr);
+                     float2 *const *work, Prof *prof = nullptr, bool start = true,
+                     bool finish = true);
+
+// Device bytes a plan for `cfg` will hold (fields, tables, tensor), without
+// allocating; used for admission control.
+size_t estimate_plan_bytes(const mmnlse_config &cfg);
 
 }  // namespace mmnlse
+
+struct mmnlse_ctx {
+  mmnlse::Plan *pl;
+};
