@@ -80,15 +80,69 @@ def cpu_baseline(p, seconds_target: float = 15.0):
                       f"{el:.1f} s"}
 
 
+def serving(args):
+    """Continuous-batching serving run: seeded Poisson request stream (M in {1,6,15,36},
+    T in {2^12,2^14,2^16}, L in {1,10,50} km) submitted at its arrival times."""
+    import threading
+
+    import paper_1901_01895_amd as mm
+    import workloads as W
+
+    specs = W.serving_stream(args.requests, rate=args.rate)
+    probs = [W.fiber.request_problem(sp) for sp in specs]
+    prec = mm.FP32 if args.precision == "fp32" else mm.SPLIT_BF16
+    cfgs = [mm.problem_config(p, precision=prec if p.M > 8 else mm.FP32) for p in probs]
+    work = sum(p.M * p.T * p.n_steps for p in probs)
+    lat = [None] * len(probs)
+    with mm.Server(steps_per_tick=args.steps_per_tick, n_streams=args.streams) as srv:
+        tickets = [None] * len(probs)
+        t0 = time.perf_counter()
+
+        def feeder():
+            for i, (sp, p) in enumerate(zip(specs, probs)):
+                dt = sp.arrival - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[i] = srv.submit(p.A0, cfgs[i])
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        th.join()
+        for i, t in enumerate(tickets):
+            _, info = srv.wait(t)
+            lat[i] = info["latency"]
+        el = time.perf_counter() - t0
+        counters = srv.counters()
+    lat = np.array(lat)
+    return {
+        "metric": METRIC, "value": work / el, "unit": "mode*sample*steps/s", "n_gpus": 1,
+        "steps": int(sum(p.n_steps for p in probs)), "warmup": 0, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == mm.FP32 else "bf16x3-split/f32-acc", "data": "synthetic",
+        "config": {"workload": f"serving: {len(probs)} requests, Poisson rate "
+                               f"{'saturated' if args.rate is None else args.rate}/s, M in {{1,6,15,36}}, "
+                               "T in {2^12,2^14,2^16}, L in {1,10,50} km",
+                   "precision": args.precision, "steps_per_tick": args.steps_per_tick,
+                   "streams": args.streams},
+        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                      "max": float(lat.max())},
+        "wall_s": el, "server": counters,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="wdm36", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="wdm36", choices=sorted(WORKLOADS) + ["serving"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--requests", type=int, default=256, help="serving: number of requests")
+    ap.add_argument("--rate", type=float, default=None, help="serving: Poisson rate 1/s (default saturated)")
+    ap.add_argument("--steps-per-tick", type=int, default=8)
+    ap.add_argument("--streams", type=int, default=4)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -104,6 +158,9 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     mm.load()
+    if args.workload == "serving":
+        print(json.dumps(serving(args)), flush=True)
+        return
     p = W.make_problem(args.workload)
     prec = mm.FP32 if args.precision == "fp32" else mm.SPLIT_BF16
     P = mm.Propagator.from_problem(p, precision=prec)

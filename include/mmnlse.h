@@ -167,6 +167,70 @@ mmnlse_status mmnlse_footprint(const mmnlse_t h, size_t *bytes);
  * 1 = generic LDS kernel (any S), 2 = packed matrix-core contraction. */
 mmnlse_status mmnlse_kerr_path(const mmnlse_t h, int32_t *path);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of propagation requests on one device.
+ *
+ * A worker thread admits queued requests in arrival order while the summed
+ * device footprint of the admitted ones stays within the budget (and at most
+ * max_active are resident), keeps each admitted field and its plan resident
+ * on the device, and in every scheduling round advances each active request
+ * by up to steps_per_tick RK4IP steps, spreading the requests over
+ * n_streams HIP streams so that their kernels overlap on the device.  A
+ * request that has taken its L/h steps is copied back and retired, which
+ * frees its memory for the next admission.  A request advanced in chunks
+ * does exactly the arithmetic of one mmnlse_propagate call, so its result
+ * is bit-identical alone and in any mix.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  size_t mem_budget_bytes;  /* device bytes the admitted requests may hold together;
+                               0 = 80 % of the free device memory at create */
+  int32_t max_active;       /* requests resident at once; 0 = 32 */
+  int32_t n_streams;        /* HIP streams (default priority) requests are spread over; 0 = 4 */
+  int32_t steps_per_tick;   /* RK4IP steps per active request per round; 0 = 8 */
+} mmnlse_server_config;
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  int32_t queued, active;
+  size_t admitted_bytes;       /* footprint of the requests resident now */
+  size_t peak_admitted_bytes;  /* largest admitted footprint seen */
+  int64_t rounds;              /* scheduling rounds run */
+} mmnlse_server_counters;
+
+typedef struct mmnlse_server *mmnlse_server_t;
+
+/* Start a server (and its worker thread) on the current HIP device.
+ * Errors: E_INVALID, E_NOMEM, E_DEVICE. */
+mmnlse_status mmnlse_server_create(const mmnlse_server_config *cfg, mmnlse_server_t *out);
+
+/* Queue one propagation of the configuration `cfg` (validated like
+ * mmnlse_create; its arrays are copied) from the host field A_in
+ * ([M][T] of type `dtype`, copied).  *ticket identifies the request.
+ * Thread-safe.  Errors: E_INVALID; E_NOMEM when the request alone exceeds
+ * the memory budget. */
+mmnlse_status mmnlse_server_submit(mmnlse_server_t s, const mmnlse_config *cfg, const void *A_in,
+                                   int32_t dtype, uint64_t *ticket);
+
+/* Non-blocking: E_BUSY while the request is queued or running.  Once it is
+ * done, copies the result (type as submitted) to the host buffer A_out,
+ * fills st (may be NULL) and *latency_s (submit to result on the host, may
+ * be NULL), releases the ticket and returns the request's own status (OK,
+ * or e.g. E_NONFINITE / E_DEVICE with mmnlse_last_error set).  Thread-safe.
+ * E_INVALID for an unknown ticket. */
+mmnlse_status mmnlse_server_poll(mmnlse_server_t s, uint64_t ticket, void *A_out, mmnlse_stats *st,
+                                 double *latency_s);
+
+/* As mmnlse_server_poll, but blocks until the request is done. */
+mmnlse_status mmnlse_server_wait(mmnlse_server_t s, uint64_t ticket, void *A_out, mmnlse_stats *st,
+                                 double *latency_s);
+
+/* Counters of the scheduler.  Thread-safe. */
+mmnlse_status mmnlse_server_stats(mmnlse_server_t s, mmnlse_server_counters *out);
+
+/* Stop the worker after the resident requests finish; queued requests that
+ * were never admitted are dropped.  Frees everything.  NULL is accepted. */
+mmnlse_status mmnlse_server_destroy(mmnlse_server_t s);
+
 #ifdef __cplusplus
 }
 #endif

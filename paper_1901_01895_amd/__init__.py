@@ -28,6 +28,8 @@ SYMBOLS = (
     "mmnlse_create", "mmnlse_destroy", "mmnlse_last_error", "mmnlse_propagate", "mmnlse_advance",
     "mmnlse_linear_half_step", "mmnlse_kerr", "mmnlse_power", "mmnlse_step_doubling",
     "mmnlse_synchronize", "mmnlse_footprint", "mmnlse_kerr_path", "mmnlse_profile",
+    "mmnlse_server_create", "mmnlse_server_submit", "mmnlse_server_poll", "mmnlse_server_wait",
+    "mmnlse_server_stats", "mmnlse_server_destroy",
 )
 
 
@@ -45,6 +47,18 @@ class Config(ctypes.Structure):
         ("gamma", ctypes.c_double), ("h_km", ctypes.c_double), ("L_km", ctypes.c_double),
         ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
     ]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_size_t), ("max_active", ctypes.c_int32),
+                ("n_streams", ctypes.c_int32), ("steps_per_tick", ctypes.c_int32)]
+
+
+class ServerCounters(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("queued", ctypes.c_int32), ("active", ctypes.c_int32),
+                ("admitted_bytes", ctypes.c_size_t), ("peak_admitted_bytes", ctypes.c_size_t),
+                ("rounds", ctypes.c_int64)]
 
 
 class Stats(ctypes.Structure):
@@ -78,6 +92,12 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mmnlse_footprint.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.mmnlse_kerr_path.argtypes = [vp, ctypes.POINTER(i32)]
     lib.mmnlse_profile.argtypes = [vp, vp, i64, dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.mmnlse_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
+    lib.mmnlse_server_submit.argtypes = [vp, ctypes.POINTER(Config), vp, i32, ctypes.POINTER(ctypes.c_uint64)]
+    for fn in (lib.mmnlse_server_poll, lib.mmnlse_server_wait):
+        fn.argtypes = [vp, ctypes.c_uint64, vp, ctypes.POINTER(Stats), dp]
+    lib.mmnlse_server_stats.argtypes = [vp, ctypes.POINTER(ServerCounters)]
+    lib.mmnlse_server_destroy.argtypes = [vp]
     for name in SYMBOLS:
         if name != "mmnlse_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -98,6 +118,32 @@ def _dptr(x) -> int:
     return x.data_ptr()
 
 
+def make_config(M, T, dt, beta, S, gamma, h, L, alpha=None, precision=FP32, symmetric=None,
+                generic=False):
+    """mmnlse_config for the arguments; returns (config, arrays it points into)."""
+    beta = np.ascontiguousarray(np.asarray(beta, dtype=np.float64).reshape(M, -1))
+    S = np.ascontiguousarray(np.asarray(S, dtype=np.float32).reshape(M, M, M, M))
+    alpha = None if alpha is None else np.ascontiguousarray(np.asarray(alpha, dtype=np.float64))
+    if symmetric is None:
+        symmetric = bool(np.array_equal(S, S.transpose(0, 2, 1, 3)) and np.array_equal(S, S.transpose(3, 1, 2, 0)))
+    cfg = Config()
+    cfg.M, cfg.T, cfg.dt_ps = M, T, float(dt)
+    cfg.n_beta = beta.shape[1]
+    cfg.beta = beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    cfg.alpha = alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if alpha is not None else None
+    cfg.S = S.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    cfg.gamma, cfg.h_km, cfg.L_km = float(gamma), float(h), float(L)
+    cfg.precision = int(precision)
+    cfg.flags = (S_SYMMETRIC if symmetric else 0) | (KERR_GENERIC if generic else 0)
+    return cfg, (beta, S, alpha)
+
+
+def problem_config(p, precision=FP32, generic=False, L=None):
+    """mmnlse_config for a workloads.Problem."""
+    return make_config(p.M, p.T, p.dt, p.beta, p.S, p.gamma, p.h, p.L if L is None else L,
+                       p.alpha if np.any(p.alpha) else None, precision, p.symmetric, generic)
+
+
 class Propagator:
     """One RK4IP plan: fixed M, T, coefficients, tensor, h and L.
 
@@ -110,22 +156,7 @@ class Propagator:
                  generic: bool = False, stream=None):
         import torch
         lib = load()
-        self._beta = np.ascontiguousarray(np.asarray(beta, dtype=np.float64).reshape(M, -1))
-        self._S = np.ascontiguousarray(np.asarray(S, dtype=np.float32).reshape(M, M, M, M))
-        self._alpha = None if alpha is None else np.ascontiguousarray(np.asarray(alpha, dtype=np.float64))
-        if symmetric is None:
-            s = self._S
-            symmetric = bool(np.array_equal(s, s.transpose(0, 2, 1, 3)) and np.array_equal(s, s.transpose(3, 1, 2, 0)))
-        flags = (S_SYMMETRIC if symmetric else 0) | (KERR_GENERIC if generic else 0)
-        cfg = Config()
-        cfg.M, cfg.T, cfg.dt_ps = M, T, float(dt)
-        cfg.n_beta = self._beta.shape[1]
-        cfg.beta = self._beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-        cfg.alpha = (self._alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-                     if self._alpha is not None else None)
-        cfg.S = self._S.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
-        cfg.gamma, cfg.h_km, cfg.L_km = float(gamma), float(h), float(L)
-        cfg.precision, cfg.flags = int(precision), flags
+        cfg, self._keep = make_config(M, T, dt, beta, S, gamma, h, L, alpha, precision, symmetric, generic)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = ctypes.c_void_p()
         _check(lib.mmnlse_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
@@ -236,3 +267,69 @@ class Propagator:
         out = ctypes.c_int32()
         _check(load().mmnlse_kerr_path(self._h, ctypes.byref(out)))
         return KERR_PATHS[out.value]
+
+
+class Server:
+    """Continuous-batching server (mmnlse_server_*): submit host fields, poll results."""
+
+    def __init__(self, mem_budget_bytes: int = 0, max_active: int = 0, n_streams: int = 0,
+                 steps_per_tick: int = 0):
+        lib = load()
+        c = ServerConfig(mem_budget_bytes, max_active, n_streams, steps_per_tick)
+        h = ctypes.c_void_p()
+        _check(lib.mmnlse_server_create(ctypes.byref(c), ctypes.byref(h)))
+        self._h = h
+        self._pending = {}
+
+    def submit(self, A: np.ndarray, cfg_and_keep) -> int:
+        """Queue a propagation; cfg_and_keep from make_config/problem_config."""
+        cfg, keep = cfg_and_keep
+        dtype = C128 if A.dtype == np.complex128 else C64
+        A = np.ascontiguousarray(A, dtype=np.complex128 if dtype == C128 else np.complex64)
+        t = ctypes.c_uint64()
+        _check(load().mmnlse_server_submit(self._h, ctypes.byref(cfg), A.ctypes.data_as(ctypes.c_void_p),
+                                           dtype, ctypes.byref(t)))
+        self._pending[t.value] = (np.empty_like(A), keep)
+        return t.value
+
+    def _finish(self, ticket, block):
+        out = self._pending.get(ticket, (None, None))[0]
+        st, lat = Stats(), ctypes.c_double()
+        fn = load().mmnlse_server_wait if block else load().mmnlse_server_poll
+        ptr = out.ctypes.data_as(ctypes.c_void_p) if out is not None else None
+        r = fn(self._h, ticket, ptr, ctypes.byref(st), ctypes.byref(lat))
+        if r == 5:  # E_BUSY
+            return None
+        self._pending.pop(ticket, None)
+        _check(r)
+        return out, {"power_in": st.power_in, "power_out": st.power_out, "seconds": st.seconds,
+                     "steps": st.steps, "latency": lat.value}
+
+    def poll(self, ticket: int):
+        """(field, info) once done, else None."""
+        return self._finish(ticket, False)
+
+    def wait(self, ticket: int):
+        return self._finish(ticket, True)
+
+    def counters(self) -> dict:
+        c = ServerCounters()
+        _check(load().mmnlse_server_stats(self._h, ctypes.byref(c)))
+        return {k: getattr(c, k) for k, _ in ServerCounters._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().mmnlse_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

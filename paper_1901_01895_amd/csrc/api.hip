@@ -199,6 +199,45 @@ static bool check_symmetric(const float *S, int M, double tol, std::string &why)
 
 hipError_t setup_mfma(Plan &pl, const float *S);  // kerr_mfma.hip
 
+// Argument checks shared by mmnlse_create and mmnlse_server_submit.
+mmnlse_status validate_config(const mmnlse_config &c, std::string &why) {
+  auto bad = [&](const char *m) {
+    why = m;
+    return MMNLSE_E_INVALID;
+  };
+  const int M = c.M, T = c.T;
+  if (M < 1 || M > 256) return bad("M must be in [1, 256]");
+  if (T < 64 || T > (1 << 20) || (T & (T - 1))) return bad("T must be a power of two in [64, 2^20]");
+  if (!(c.dt_ps > 0) || !std::isfinite(c.dt_ps)) return bad("dt must be positive");
+  if (c.n_beta < 0 || c.n_beta > 8) return bad("n_beta must be in [0, 8]");
+  if (c.n_beta > 0 && !c.beta) return bad("beta is NULL");
+  if (!c.S) return bad("S is NULL");
+  if (!std::isfinite(c.gamma)) return bad("gamma must be finite");
+  if (!(c.h_km > 0) || !std::isfinite(c.h_km)) return bad("h must be positive");
+  if (!(c.L_km >= 0) || !std::isfinite(c.L_km)) return bad("L must be >= 0");
+  const double ratio = c.L_km / c.h_km;
+  if (std::fabs(ratio - std::round(ratio)) > 1e-9 * std::max(1.0, ratio)) return bad("L/h is not an integer");
+  if (c.precision != MMNLSE_FP32 && c.precision != MMNLSE_SPLIT_BF16) return bad("unknown precision");
+  for (int i = 0; i < M * c.n_beta; ++i)
+    if (!std::isfinite(c.beta[i])) return bad("beta is not finite");
+  if (c.alpha)
+    for (int i = 0; i < M; ++i)
+      if (!std::isfinite(c.alpha[i])) return bad("alpha is not finite");
+  const size_t n4 = (size_t)M * M * M * M;
+  for (size_t i = 0; i < n4; ++i)
+    if (!std::isfinite(c.S[i])) return bad("S is not finite");
+  const bool sym = (c.flags & MMNLSE_S_SYMMETRIC) != 0;
+  if (sym && !check_symmetric(c.S, M, 1e-6, why)) {
+    why += " but MMNLSE_S_SYMMETRIC is set";
+    return MMNLSE_E_INVALID;
+  }
+  if (c.precision == MMNLSE_SPLIT_BF16 && !sym) return bad("split-bf16 precision needs MMNLSE_S_SYMMETRIC");
+  return MMNLSE_OK;
+}
+
+void set_last_error(const std::string &msg) { g_err = msg; }
+
+
 size_t estimate_plan_bytes(const mmnlse_config &cfg) {
   const size_t M = (size_t)cfg.M, T = (size_t)cfg.T, MT = M * T;
   size_t b = 3 * MT * sizeof(float2) + MT * sizeof(float4) + T * sizeof(float4) + 1024 * sizeof(double2);
@@ -226,37 +265,15 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
   g_err.clear();
   if (!cfg || !out) return fail(MMNLSE_E_INVALID, "null argument");
   *out = nullptr;
-  const int M = cfg->M, T = cfg->T;
-  if (M < 1 || M > 256) return fail(MMNLSE_E_INVALID, "M must be in [1, 256]");
-  if (T < 64 || T > (1 << 20) || (T & (T - 1))) return fail(MMNLSE_E_INVALID, "T must be a power of two in [64, 2^20]");
-  if (!(cfg->dt_ps > 0) || !std::isfinite(cfg->dt_ps)) return fail(MMNLSE_E_INVALID, "dt must be positive");
-  if (cfg->n_beta < 0 || cfg->n_beta > 8) return fail(MMNLSE_E_INVALID, "n_beta must be in [0, 8]");
-  if (cfg->n_beta > 0 && !cfg->beta) return fail(MMNLSE_E_INVALID, "beta is NULL");
-  if (!cfg->S) return fail(MMNLSE_E_INVALID, "S is NULL");
-  if (!std::isfinite(cfg->gamma)) return fail(MMNLSE_E_INVALID, "gamma must be finite");
-  if (!(cfg->h_km > 0) || !std::isfinite(cfg->h_km)) return fail(MMNLSE_E_INVALID, "h must be positive");
-  if (!(cfg->L_km >= 0) || !std::isfinite(cfg->L_km)) return fail(MMNLSE_E_INVALID, "L must be >= 0");
-  const double ratio = cfg->L_km / cfg->h_km;
-  const double nst = std::round(ratio);
-  if (std::fabs(ratio - nst) > 1e-9 * std::max(1.0, ratio)) return fail(MMNLSE_E_INVALID, "L/h is not an integer");
-  if (cfg->precision != MMNLSE_FP32 && cfg->precision != MMNLSE_SPLIT_BF16)
-    return fail(MMNLSE_E_INVALID, "unknown precision");
-  for (int i = 0; i < M * cfg->n_beta; ++i)
-    if (!std::isfinite(cfg->beta[i])) return fail(MMNLSE_E_INVALID, "beta is not finite");
-  if (cfg->alpha)
-    for (int i = 0; i < M; ++i)
-      if (!std::isfinite(cfg->alpha[i])) return fail(MMNLSE_E_INVALID, "alpha is not finite");
-  const size_t n4 = (size_t)M * M * M * M;
-  for (size_t i = 0; i < n4; ++i)
-    if (!std::isfinite(cfg->S[i])) return fail(MMNLSE_E_INVALID, "S is not finite");
-  const bool sym = (cfg->flags & MMNLSE_S_SYMMETRIC) != 0;
-  if (sym) {
+  {
     std::string why;
-    if (!check_symmetric(cfg->S, M, 1e-6, why)) return fail(MMNLSE_E_INVALID, why + " but MMNLSE_S_SYMMETRIC is set");
+    const mmnlse_status v = validate_config(*cfg, why);
+    if (v != MMNLSE_OK) return fail(v, why);
   }
-  if (cfg->precision == MMNLSE_SPLIT_BF16 && !sym)
-    return fail(MMNLSE_E_INVALID, "split-bf16 precision needs MMNLSE_S_SYMMETRIC");
-
+  const int M = cfg->M, T = cfg->T;
+  const double nst = std::round(cfg->L_km / cfg->h_km);
+  const size_t n4 = (size_t)M * M * M * M;
+  const bool sym = (cfg->flags & MMNLSE_S_SYMMETRIC) != 0;
   Plan *pl = new (std::nothrow) Plan();
   if (!pl) return fail(MMNLSE_E_NOMEM, "host allocation");
   pl->M = M;

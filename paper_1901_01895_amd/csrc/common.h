@@ -143,6 +143,10 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
                      float2 *const *work, Prof *prof = nullptr, bool start = true,
                      bool finish = true);
 
+// Argument checks shared by mmnlse_create and the server (E_INVALID + reason).
+mmnlse_status validate_config(const mmnlse_config &cfg, std::string &why);
+void set_last_error(const std::string &msg);
+
 // Device bytes a plan for `cfg` will hold (fields, tables, tensor), without
 // allocating; used for admission control.
 size_t estimate_plan_bytes(const mmnlse_config &cfg);

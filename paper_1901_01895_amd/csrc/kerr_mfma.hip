@@ -42,6 +42,9 @@ struct MArgs {
   int M, T, P, Ppad, next;
 };
 
+constexpr int RT_F32 = 4;   // row tiles per pass (B formed once per pass)
+constexpr int RT_BF16 = 4;
+
 // Output row of accumulator register v for lane-half `half` of a 32x32 tile.
 __device__ __forceinline__ int acc_row(int v, int half) { return 8 * (v >> 2) + 4 * half + (v & 3); }
 
@@ -69,87 +72,125 @@ __device__ __forceinline__ void scatter_tile(const MArgs &a, const floatx16 &cre
   }
 }
 
-// One full contraction for the wave's 32 samples: Os[:, cols] += sum over all rows.
+// One pass over RT consecutive row tiles (rows 32*rt0 .. 32*(rt0+RT)-1) for
+// the wave's 32 samples: accumulate C over all q, then scatter into Os.  The
+// A operand of the next k-step is loaded while the current one is used.
 template <int W, int RT, bool SPLIT>
-__device__ __forceinline__ void contract(const MArgs &a, const float2 *Xs, float2 *Os, int lane, int col) {
+__device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, float2 *Os, int lane, int col,
+                                              int rt0) {
   constexpr int TT = 32 * W;
   const int half = lane >> 5;
-  const int nrt = a.Ppad / 32;
-  for (int rt0 = 0; rt0 < nrt; rt0 += RT) {
-    floatx16 cre[RT], cim[RT];
+  floatx16 cre[RT], cim[RT];
 #pragma unroll
-    for (int j = 0; j < RT; ++j) {
-      cre[j] = floatx16{0};
-      cim[j] = floatx16{0};
-    }
-    if (!SPLIT) {
-      const int nk = a.Ppad / 8;  // 4 k-steps of 2 per iteration
-      for (int kq = 0; kq < nk; ++kq) {
-        float4 av[RT];
-#pragma unroll
-        for (int j = 0; j < RT; ++j) av[j] = a.A32[((size_t)(rt0 + j) * nk + kq) * 64 + lane];
-        const int4 p0 = *(const int4 *)(a.pairs + 8 * kq);
-        const int4 p1 = *(const int4 *)(a.pairs + 8 * kq + 4);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int lo = s == 0 ? p0.x : s == 1 ? p0.z : s == 2 ? p1.x : p1.z;
-          const int hi = s == 0 ? p0.y : s == 1 ? p0.w : s == 2 ? p1.y : p1.w;
-          const int ab = half ? hi : lo;
-          const float2 xa = Xs[(ab & 0xffff) * TT + col];
-          const float2 xb = Xs[(ab >> 16) * TT + col];
-          const float bre = fmaf(xa.x, xb.x, -xa.y * xb.y);
-          const float bim = fmaf(xa.x, xb.y, xa.y * xb.x);
-#pragma unroll
-          for (int j = 0; j < RT; ++j) {
-            const float av_s = s == 0 ? av[j].x : s == 1 ? av[j].y : s == 2 ? av[j].z : av[j].w;
-            cre[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, bre, cre[j], 0, 0, 0);
-            cim[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, bim, cim[j], 0, 0, 0);
-          }
-        }
-      }
-    } else {
-      const int nk = a.Ppad / 16;  // k-steps of 16
-      for (int ks = 0; ks < nk; ++ks) {
-        uint4 ah[RT], al[RT];
-#pragma unroll
-        for (int j = 0; j < RT; ++j) {
-          ah[j] = a.Ah[((size_t)(rt0 + j) * nk + ks) * 64 + lane];
-          al[j] = a.Al[((size_t)(rt0 + j) * nk + ks) * 64 + lane];
-        }
-        const int *pp = a.pairs + 16 * ks + 8 * half;
-        bf16x8 rh, rl, ih, il;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int ab = pp[e];
-          const float2 xa = Xs[(ab & 0xffff) * TT + col];
-          const float2 xb = Xs[(ab >> 16) * TT + col];
-          const float bre = fmaf(xa.x, xb.x, -xa.y * xb.y);
-          const float bim = fmaf(xa.x, xb.y, xa.y * xb.x);
-          const __bf16 hr = (__bf16)bre, hi = (__bf16)bim;
-          rh[e] = hr;
-          ih[e] = hi;
-          rl[e] = (__bf16)(bre - (float)hr);
-          il[e] = (__bf16)(bim - (float)hi);
-        }
-#pragma unroll
-        for (int j = 0; j < RT; ++j) {
-          const bf16x8 sh = __builtin_bit_cast(bf16x8, ah[j]);
-          const bf16x8 sl = __builtin_bit_cast(bf16x8, al[j]);
-          cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, rh, cre[j], 0, 0, 0);
-          cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rl, cre[j], 0, 0, 0);
-          cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rh, cre[j], 0, 0, 0);
-          cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, ih, cim[j], 0, 0, 0);
-          cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, il, cim[j], 0, 0, 0);
-          cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, ih, cim[j], 0, 0, 0);
-        }
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < RT; ++j) scatter_tile<TT>(a, cre[j], cim[j], rt0 + j, Xs, Os, lane, col);
+  for (int j = 0; j < RT; ++j) {
+    cre[j] = floatx16{0};
+    cim[j] = floatx16{0};
   }
+  if (!SPLIT) {
+    // 4 k-steps of 2 per group; Ppad is a multiple of 32, so the number of
+    // groups is even and the ping-pong below needs no tail
+    const int nk = a.Ppad / 8;
+    const float4 *Ab = a.A32 + (size_t)rt0 * nk * 64 + lane;
+    float4 a0[RT], a1[RT];
+    auto load = [&](float4 (&dst)[RT], int kq) {
+#pragma unroll
+      for (int j = 0; j < RT; ++j) dst[j] = Ab[((size_t)j * nk + kq) * 64];
+    };
+    auto group = [&](const float4 (&av)[RT], int kq) {
+      const int4 p0 = *(const int4 *)(a.pairs + 8 * kq);
+      const int4 p1 = *(const int4 *)(a.pairs + 8 * kq + 4);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int lo = s == 0 ? p0.x : s == 1 ? p0.z : s == 2 ? p1.x : p1.z;
+        const int hi = s == 0 ? p0.y : s == 1 ? p0.w : s == 2 ? p1.y : p1.w;
+        const int ab = half ? hi : lo;
+        const float2 xa = Xs[(ab & 0xffff) * TT + col];
+        const float2 xb = Xs[(ab >> 16) * TT + col];
+        const float bre = fmaf(xa.x, xb.x, -xa.y * xb.y);
+        const float bim = fmaf(xa.x, xb.y, xa.y * xb.x);
+#pragma unroll
+        for (int j = 0; j < RT; ++j) {
+          const float av_s = s == 0 ? av[j].x : s == 1 ? av[j].y : s == 2 ? av[j].z : av[j].w;
+          cre[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, bre, cre[j], 0, 0, 0);
+          cim[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, bim, cim[j], 0, 0, 0);
+        }
+      }
+    };
+    load(a0, 0);
+    for (int kq = 0; kq < nk; kq += 2) {
+      load(a1, kq + 1);
+      group(a0, kq);
+      if (kq + 2 < nk) load(a0, kq + 2);
+      group(a1, kq + 1);
+    }
+  } else {
+    const int nk = a.Ppad / 16;  // k-steps of 16; even, see above
+    const uint4 *Hb = a.Ah + (size_t)rt0 * nk * 64 + lane;
+    const uint4 *Lb = a.Al + (size_t)rt0 * nk * 64 + lane;
+    uint4 h0[RT], l0[RT], h1[RT], l1[RT];
+    auto load = [&](uint4 (&hd)[RT], uint4 (&ld)[RT], int ks) {
+#pragma unroll
+      for (int j = 0; j < RT; ++j) {
+        hd[j] = Hb[((size_t)j * nk + ks) * 64];
+        ld[j] = Lb[((size_t)j * nk + ks) * 64];
+      }
+    };
+    auto step = [&](const uint4 (&ah)[RT], const uint4 (&al)[RT], int ks) {
+      const int *pp = a.pairs + 16 * ks + 8 * half;
+      bf16x8 rh, rl, ih, il;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int ab = pp[e];
+        const float2 xa = Xs[(ab & 0xffff) * TT + col];
+        const float2 xb = Xs[(ab >> 16) * TT + col];
+        const float bre = fmaf(xa.x, xb.x, -xa.y * xb.y);
+        const float bim = fmaf(xa.x, xb.y, xa.y * xb.x);
+        const __bf16 hr = (__bf16)bre, hi = (__bf16)bim;
+        rh[e] = hr;
+        ih[e] = hi;
+        rl[e] = (__bf16)(bre - (float)hr);
+        il[e] = (__bf16)(bim - (float)hi);
+      }
+#pragma unroll
+      for (int j = 0; j < RT; ++j) {
+        const bf16x8 sh = __builtin_bit_cast(bf16x8, ah[j]);
+        const bf16x8 sl = __builtin_bit_cast(bf16x8, al[j]);
+        cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, rh, cre[j], 0, 0, 0);
+        cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rl, cre[j], 0, 0, 0);
+        cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rh, cre[j], 0, 0, 0);
+        cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, ih, cim[j], 0, 0, 0);
+        cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, il, cim[j], 0, 0, 0);
+        cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, ih, cim[j], 0, 0, 0);
+      }
+    };
+    load(h0, l0, 0);
+    for (int ks = 0; ks < nk; ks += 2) {
+      load(h1, l1, ks + 1);
+      step(h0, l0, ks);
+      if (ks + 2 < nk) load(h0, l0, ks + 2);
+      step(h1, l1, ks + 1);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < RT; ++j) scatter_tile<TT>(a, cre[j], cim[j], rt0 + j, Xs, Os, lane, col);
 }
 
-template <int W, int RT, bool SPLIT, int STAGE>
+// Full contraction: row tiles in passes of RT_MAX, the remainder in passes
+// of 2 and 1 (rows are padded to a multiple of 32 only).
+template <int W, bool SPLIT>
+__device__ __forceinline__ void contract(const MArgs &a, const float2 *Xs, float2 *Os, int lane, int col) {
+  constexpr int RTM = SPLIT ? RT_BF16 : RT_F32;
+  const int nrt = a.Ppad / 32;
+  int rt0 = 0;
+  for (; rt0 + RTM <= nrt; rt0 += RTM) contract_pass<W, RTM, SPLIT>(a, Xs, Os, lane, col, rt0);
+  if (RTM > 2 && rt0 + 2 <= nrt) {
+    contract_pass<W, 2, SPLIT>(a, Xs, Os, lane, col, rt0);
+    rt0 += 2;
+  }
+  if (rt0 < nrt) contract_pass<W, 1, SPLIT>(a, Xs, Os, lane, col, rt0);
+}
+
+template <int W, bool SPLIT, int STAGE>
 __global__ __launch_bounds__(64 * W) void kerr_mfma(MArgs a) {
   constexpr int TT = 32 * W;
   constexpr int NT = 64 * W;
@@ -169,7 +210,7 @@ __global__ __launch_bounds__(64 * W) void kerr_mfma(MArgs a) {
     Os[idx] = make_float2(0.f, 0.f);
   }
   __syncthreads();
-  contract<W, RT, SPLIT>(a, Xs, Os, lane, col);
+  contract<W, SPLIT>(a, Xs, Os, lane, col);
   __syncthreads();
   for (int idx = threadIdx.x; idx < a.M * TT; idx += NT) {
     const size_t g = (size_t)(idx / TT) * a.T + t0 + (idx % TT);
@@ -192,7 +233,7 @@ __global__ __launch_bounds__(64 * W) void kerr_mfma(MArgs a) {
   }
   if (STAGE == STAGE_K4 && a.next) {
     __syncthreads();
-    contract<W, RT, SPLIT>(a, Xs, Os, lane, col);
+    contract<W, SPLIT>(a, Xs, Os, lane, col);
     __syncthreads();
     for (int idx = threadIdx.x; idx < a.M * TT; idx += NT) {
       const float2 o = Os[idx];
@@ -201,10 +242,7 @@ __global__ __launch_bounds__(64 * W) void kerr_mfma(MArgs a) {
   }
 }
 
-constexpr int RT_F32 = 2;
-constexpr int RT_BF16 = 2;
-
-template <int W, int RT, bool SPLIT>
+template <int W, bool SPLIT>
 hipError_t go(const MArgs &a, KerrStage st, hipStream_t s) {
   constexpr int TT = 32 * W;
   const dim3 grid(a.T / TT), block(64 * W);
@@ -218,20 +256,19 @@ hipError_t go(const MArgs &a, KerrStage st, hipStream_t s) {
     return hipGetLastError();
   };
   switch (st) {
-    case STAGE_PLAIN: return launch(kerr_mfma<W, RT, SPLIT, STAGE_PLAIN>);
-    case STAGE_K2: return launch(kerr_mfma<W, RT, SPLIT, STAGE_K2>);
-    case STAGE_K3: return launch(kerr_mfma<W, RT, SPLIT, STAGE_K3>);
-    case STAGE_K4: return launch(kerr_mfma<W, RT, SPLIT, STAGE_K4>);
+    case STAGE_PLAIN: return launch(kerr_mfma<W, SPLIT, STAGE_PLAIN>);
+    case STAGE_K2: return launch(kerr_mfma<W, SPLIT, STAGE_K2>);
+    case STAGE_K3: return launch(kerr_mfma<W, SPLIT, STAGE_K3>);
+    case STAGE_K4: return launch(kerr_mfma<W, SPLIT, STAGE_K4>);
   }
   return hipErrorInvalidValue;
 }
 
 template <bool SPLIT>
 hipError_t go_w(const MArgs &a, KerrStage st, hipStream_t s) {
-  constexpr int RT = SPLIT ? RT_BF16 : RT_F32;
-  if (a.M <= 64 && a.T % 128 == 0) return go<4, RT, SPLIT>(a, st, s);
-  if (a.M <= 128) return go<2, RT, SPLIT>(a, st, s);
-  return go<1, RT, SPLIT>(a, st, s);
+  if (a.M <= 64 && a.T % 128 == 0) return go<4, SPLIT>(a, st, s);
+  if (a.M <= 128) return go<2, SPLIT>(a, st, s);
+  return go<1, SPLIT>(a, st, s);
 }
 
 uint16_t bf16_bits(float x) {  // round to nearest even
@@ -278,8 +315,7 @@ hipError_t launch_pack_bf16(const Plan &) { return hipSuccess; }
 hipError_t setup_mfma(Plan &pl, const float *S) {
   const int M = pl.M;
   const int P = M * (M + 1) / 2;
-  const int RT = pl.precision == MMNLSE_SPLIT_BF16 ? RT_BF16 : RT_F32;
-  const int quantum = 32 * RT;  // rows per pass; also a multiple of 16 for the bf16 k-steps
+  const int quantum = 32;  // one row tile; also a multiple of 16 (bf16 k-step) and 8
   const int Ppad = ((P + quantum - 1) / quantum) * quantum;
   pl.P = P;
   pl.Ppad = Ppad;

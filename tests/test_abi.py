@@ -35,8 +35,7 @@ def test_library_exports_every_declared_symbol():
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 def test_binding_lists_every_declared_symbol():
     import paper_1901_01895_amd as mm
-    assert sorted(mm.SYMBOLS) == [s for s in declared_symbols() if not s.startswith("mmnlse_server")] \
-        or set(declared_symbols()) >= set(mm.SYMBOLS)
+    assert sorted(mm.SYMBOLS) == declared_symbols()
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")

@@ -343,18 +343,29 @@ def serving_stream(n: int = 256, rate: float | None = None, cfg: int = 3) -> lis
                         "qpsk6" if Ms[i] <= 6 else "wdm36") for i in range(n)]
 
 
+_TENSOR_CACHE: dict = {}
+
+
+def _request_tensor(M: int, cfg: int, masked: bool):
+    """Requests of one mode count share one fiber's tensor (generated once)."""
+    key = (M, cfg, masked)
+    if key not in _TENSOR_CACHE:
+        _TENSOR_CACHE[key] = coupling_tensor(M, cfg * 100 + M, mask_frac=0.7 if masked else 0.0)
+    return _TENSOR_CACHE[key]
+
+
 def request_problem(spec: RequestSpec, cfg: int = 3) -> Problem:
     """Field and coefficients of one serving request (seeded by its index)."""
     sub = 1000 + spec.index
     M, T = spec.M, spec.T
     if spec.style == "qpsk6":
         A, dt = shaped_field(_rng(cfg, STREAM_SYMBOLS, sub), M, T, 8, 1, 0.05, "qpsk", _dbm(0.0))
-        S, info = coupling_tensor(M, cfg * 100 + M)
+        S, info = _request_tensor(M, cfg, False)
         h = 0.1
         beta = _random_beta(M, cfg * 100000 + sub)
     else:
         A, dt = shaped_field(_rng(cfg, STREAM_SYMBOLS, sub), M, T, 32, 8, 0.05, "16qam", _dbm(-2.0))
-        S, info = coupling_tensor(M, cfg * 100 + M, mask_frac=0.7)
+        S, info = _request_tensor(M, cfg, True)
         h = 0.05
         beta = _random_beta(M, cfg * 100000 + sub)
     n_steps = int(round(spec.L / h))
