@@ -15,6 +15,7 @@ from .rk4ip import (  # noqa: F401
     half_step_propagator,
     kerr_term,
     KerrGeneric,
+    KerrManakov,
     KerrPacked,
     linear_operator,
     power,

@@ -34,7 +34,9 @@ Pins (tests/test_oracle_pins.py, all CPU):
 * self-phase modulation exp(i gamma |A|^2 z) and CW + beta0 phase (IP frame);
 * classical RK4 reduction when the linear operator vanishes;
 * fundamental soliton and 4th-order convergence under step halving;
-* packed symmetric Kerr == generic Kerr for symmetric S.
+* packed symmetric Kerr == generic Kerr for symmetric S;
+* Manakov/XPM form of Eq. (1): exact per-mode phase rotation without
+  dispersion, and equality with the tensor form S_plmn = kappa_pm d_lp d_mn.
 
 Units: t in ps, z in km, power in W, w in rad/ps, beta_n in ps^n/km.
 """
@@ -47,7 +49,7 @@ import numpy as np
 
 __all__ = [
     "time_grid", "angular_frequencies", "linear_operator", "half_step_propagator",
-    "apply_linear", "KerrGeneric", "KerrPacked", "kerr_term", "rk4ip_step",
+    "apply_linear", "KerrGeneric", "KerrPacked", "KerrManakov", "kerr_term", "rk4ip_step",
     "propagate", "power", "step_doubling_estimate",
 ]
 
@@ -169,6 +171,24 @@ class KerrPacked:
             np.add.at(o, b[self.off], C[self.off] * np.conj(x[a[self.off]]))
             out[:, s:s + self.chunk] = 1j * self.gamma * o
         return out
+
+
+class KerrManakov:
+    """The paper's own nonlinear operator, Eq. (1):
+    N_a = i gamma (kappa_aa |X_a|^2 + sum_{b != a} kappa_ab |X_b|^2) X_a
+        = i gamma (sum_b kappa_ab |X_b|^2) X_a,
+    with a real coupling matrix kappa (rows = modes incl. polarizations)."""
+
+    def __init__(self, kappa: np.ndarray, gamma: float):
+        self.kappa = np.asarray(kappa, dtype=np.float64)
+        if self.kappa.ndim != 2 or self.kappa.shape[0] != self.kappa.shape[1]:
+            raise ValueError("kappa must be [M,M]")
+        self.gamma = float(gamma)
+
+    def __call__(self, X: np.ndarray) -> np.ndarray:
+        X = np.asarray(X, dtype=np.complex128)
+        phase = self.kappa @ (np.abs(X) ** 2)        # [a, t]
+        return 1j * self.gamma * phase * X
 
 
 def kerr_term(X: np.ndarray, S: np.ndarray, gamma: float) -> np.ndarray:

@@ -284,6 +284,49 @@ def test_step_doubling_estimate_tracks_true_error():
 
 
 # ----------------------------------------------------------------------------
+# the paper's own Manakov / XPM nonlinear operator (Eq. 1)
+# ----------------------------------------------------------------------------
+
+def test_manakov_form_rotates_each_mode_exactly_without_dispersion():
+    """|A_b| is invariant under N_a = i g (sum_b k_ab |A_b|^2) A_a, so without dispersion
+    A_a(z) = A_a(0) exp(i g sum_b k_ab |A_b(0)|^2 z); RK4 converges to it at 4th order."""
+    rng = _rng(20)
+    M, T = 5, 64
+    kappa = rng.uniform(0.2, 1.0, (M, M))
+    kappa = 0.5 * (kappa + kappa.T)
+    A0 = 0.8 * _crandn(rng, M, T)
+    g, z = 1.3, 0.5
+    exact = A0 * np.exp(1j * g * (kappa @ np.abs(A0) ** 2) * z)
+    errs = []
+    for n in (80, 160):
+        out = oracle.propagate(A0, np.zeros((M, 1)), None, None, g, 1.0, z / n, n,
+                               kerr=oracle.KerrManakov(kappa, g))
+        errs.append(_rel(out, exact))
+    assert errs[-1] < 5e-8
+    assert 13.0 < errs[0] / errs[1] < 17.5
+
+
+def test_manakov_equals_tensor_form():
+    """Eq. (1) is the tensor form with S_plmn = kappa_pm delta_lp delta_mn, also for a
+    non-symmetric kappa (output p, conjugated n = m)."""
+    rng = _rng(21)
+    M = 4
+    kappa = rng.standard_normal((M, M))
+    S = np.zeros((M,) * 4)
+    for p in range(M):
+        for m in range(M):
+            S[p, p, m, m] = kappa[p, m]
+    X = _crandn(rng, M, 33)
+    assert _rel(oracle.KerrManakov(kappa, 0.9)(X), oracle.kerr_term(X, S, 0.9)) < 1e-14
+
+
+def test_manakov_single_mode_is_spm():
+    X = _crandn(_rng(22), 1, 16)
+    got = oracle.KerrManakov(np.array([[1.0]]), 2.0)(X)
+    assert _rel(got, 2j * np.abs(X) ** 2 * X) < 1e-15
+
+
+# ----------------------------------------------------------------------------
 # mutants: plausible mistakes planted in a copy of the oracle must fail a pin
 # ----------------------------------------------------------------------------
 
