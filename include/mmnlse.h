@@ -67,6 +67,12 @@ typedef enum { MMNLSE_C64 = 0, MMNLSE_C128 = 1 } mmnlse_dtype;
 #define MMNLSE_S_SYMMETRIC 0x1u
 /* Force the unpacked per-sample Kerr kernel (any S). */
 #define MMNLSE_KERR_GENERIC 0x2u
+/* Use the paper's own nonlinear operator of Eq. (1) (Manakov / XPM form)
+ * instead of the tensor form: N_a = i gamma (sum_b kappa_ab |A_b|^2) A_a with
+ * the real [M][M] matrix `kappa` (kappa_aa intramodal, kappa_ab intermodal
+ * coefficients; rows are spatial and polarization modes).  S is ignored and
+ * may be NULL.  FP32 only. */
+#define MMNLSE_KERR_MANAKOV 0x4u
 
 typedef struct {
   int32_t M;             /* modes (rows), 1 <= M <= 256 */
@@ -75,12 +81,15 @@ typedef struct {
   int32_t n_beta;        /* number of Taylor coefficients beta_0..beta_{n_beta-1}, 0..8 */
   const double *beta;    /* [M][n_beta] host array, ps^n/km; copied at create */
   const double *alpha;   /* [M] host array, power attenuation in 1/km, or NULL for 0 */
-  const float *S;        /* [M][M][M][M] host array, index order (p,l,m,n); copied */
+  const float *S;        /* [M][M][M][M] host array, index order (p,l,m,n); copied
+                            (may be NULL with MMNLSE_KERR_MANAKOV) */
   double gamma;          /* nonlinear coefficient, 1/(W km) */
   double h_km;           /* step size, > 0 */
   double L_km;           /* fiber length; L/h must be an integer within 1e-9 relative */
   int32_t precision;     /* mmnlse_precision */
-  uint32_t flags;        /* MMNLSE_S_SYMMETRIC | MMNLSE_KERR_GENERIC */
+  uint32_t flags;        /* MMNLSE_S_SYMMETRIC | MMNLSE_KERR_GENERIC | MMNLSE_KERR_MANAKOV */
+  const float *kappa;    /* [M][M] host array (row a, column b), used with
+                            MMNLSE_KERR_MANAKOV, else ignored; copied */
 } mmnlse_config;
 
 typedef struct {
@@ -164,7 +173,8 @@ mmnlse_status mmnlse_synchronize(mmnlse_t h);
 mmnlse_status mmnlse_footprint(const mmnlse_t h, size_t *bytes);
 
 /* Kernel used for the Kerr term: 0 = per-sample register kernel (M <= 8),
- * 1 = generic LDS kernel (any S), 2 = packed matrix-core contraction. */
+ * 1 = generic LDS kernel (any S), 2 = packed matrix-core contraction,
+ * 3 = Manakov / XPM form of Eq. (1). */
 mmnlse_status mmnlse_kerr_path(const mmnlse_t h, int32_t *path);
 
 /* ------------------------------------------------------------------------

@@ -18,8 +18,8 @@ LIB_PATH = os.path.join(_PKG, "libmmnlse.so")
 
 FP32, SPLIT_BF16 = 0, 1
 C64, C128 = 0, 1
-S_SYMMETRIC, KERR_GENERIC = 0x1, 0x2
-KERR_PATHS = {0: "small", 1: "tiled", 2: "mfma"}
+S_SYMMETRIC, KERR_GENERIC, KERR_MANAKOV = 0x1, 0x2, 0x4
+KERR_PATHS = {0: "small", 1: "tiled", 2: "mfma", 3: "manakov"}
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NONFINITE", 5: "E_BUSY",
           6: "E_UNSUPPORTED"}
@@ -46,6 +46,7 @@ class Config(ctypes.Structure):
         ("alpha", ctypes.POINTER(ctypes.c_double)), ("S", ctypes.POINTER(ctypes.c_float)),
         ("gamma", ctypes.c_double), ("h_km", ctypes.c_double), ("L_km", ctypes.c_double),
         ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("kappa", ctypes.POINTER(ctypes.c_float)),
     ]
 
 
@@ -119,29 +120,39 @@ def _dptr(x) -> int:
 
 
 def make_config(M, T, dt, beta, S, gamma, h, L, alpha=None, precision=FP32, symmetric=None,
-                generic=False):
-    """mmnlse_config for the arguments; returns (config, arrays it points into)."""
+                generic=False, kappa=None):
+    """mmnlse_config for the arguments; returns (config, arrays it points into).
+
+    With ``kappa`` ([M, M]) the paper's Manakov / XPM nonlinear operator of
+    Eq. (1) is used and S is ignored (may be None)."""
     beta = np.ascontiguousarray(np.asarray(beta, dtype=np.float64).reshape(M, -1))
-    S = np.ascontiguousarray(np.asarray(S, dtype=np.float32).reshape(M, M, M, M))
     alpha = None if alpha is None else np.ascontiguousarray(np.asarray(alpha, dtype=np.float64))
-    if symmetric is None:
-        symmetric = bool(np.array_equal(S, S.transpose(0, 2, 1, 3)) and np.array_equal(S, S.transpose(3, 1, 2, 0)))
+    if kappa is not None:
+        kappa = np.ascontiguousarray(np.asarray(kappa, dtype=np.float32).reshape(M, M))
+        S, symmetric = None, False
+    else:
+        S = np.ascontiguousarray(np.asarray(S, dtype=np.float32).reshape(M, M, M, M))
+        if symmetric is None:
+            symmetric = bool(np.array_equal(S, S.transpose(0, 2, 1, 3)) and np.array_equal(S, S.transpose(3, 1, 2, 0)))
     cfg = Config()
     cfg.M, cfg.T, cfg.dt_ps = M, T, float(dt)
     cfg.n_beta = beta.shape[1]
     cfg.beta = beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     cfg.alpha = alpha.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if alpha is not None else None
-    cfg.S = S.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    cfg.S = S.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if S is not None else None
+    cfg.kappa = kappa.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if kappa is not None else None
     cfg.gamma, cfg.h_km, cfg.L_km = float(gamma), float(h), float(L)
     cfg.precision = int(precision)
-    cfg.flags = (S_SYMMETRIC if symmetric else 0) | (KERR_GENERIC if generic else 0)
-    return cfg, (beta, S, alpha)
+    cfg.flags = ((S_SYMMETRIC if symmetric else 0) | (KERR_GENERIC if generic else 0)
+                 | (KERR_MANAKOV if kappa is not None else 0))
+    return cfg, (beta, S, alpha, kappa)
 
 
 def problem_config(p, precision=FP32, generic=False, L=None):
     """mmnlse_config for a workloads.Problem."""
     return make_config(p.M, p.T, p.dt, p.beta, p.S, p.gamma, p.h, p.L if L is None else L,
-                       p.alpha if np.any(p.alpha) else None, precision, p.symmetric, generic)
+                       p.alpha if np.any(p.alpha) else None, precision, p.symmetric, generic,
+                       getattr(p, "kappa", None))
 
 
 class Propagator:
@@ -153,10 +164,11 @@ class Propagator:
 
     def __init__(self, M: int, T: int, dt: float, beta, S, gamma: float, h: float, L: float,
                  alpha=None, precision: int = FP32, symmetric: bool | None = None,
-                 generic: bool = False, stream=None):
+                 generic: bool = False, stream=None, kappa=None):
         import torch
         lib = load()
-        cfg, self._keep = make_config(M, T, dt, beta, S, gamma, h, L, alpha, precision, symmetric, generic)
+        cfg, self._keep = make_config(M, T, dt, beta, S, gamma, h, L, alpha, precision, symmetric, generic,
+                                      kappa)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = ctypes.c_void_p()
         _check(lib.mmnlse_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
@@ -171,7 +183,8 @@ class Propagator:
                      stream=None):
         return cls(p.M, p.T, p.dt, p.beta, p.S, p.gamma, p.h, p.L if L is None else L,
                    alpha=p.alpha if np.any(p.alpha) else None, precision=precision,
-                   symmetric=p.symmetric, generic=generic, stream=stream)
+                   symmetric=p.symmetric, generic=generic, stream=stream,
+                   kappa=getattr(p, "kappa", None))
 
     # ------------------------------------------------------------------
     def close(self):

@@ -97,6 +97,7 @@ static void free_plan(Plan *pl) {
   hipFree(pl->E);
   hipFree(pl->E2);
   hipFree(pl->Sg);
+  hipFree(pl->kappa);
   hipFree(pl->Sp);
   hipFree(pl->Sph);
   hipFree(pl->Spl);
@@ -211,7 +212,14 @@ mmnlse_status validate_config(const mmnlse_config &c, std::string &why) {
   if (!(c.dt_ps > 0) || !std::isfinite(c.dt_ps)) return bad("dt must be positive");
   if (c.n_beta < 0 || c.n_beta > 8) return bad("n_beta must be in [0, 8]");
   if (c.n_beta > 0 && !c.beta) return bad("beta is NULL");
-  if (!c.S) return bad("S is NULL");
+  const bool manakov = (c.flags & MMNLSE_KERR_MANAKOV) != 0;
+  if (manakov && !c.kappa) return bad("kappa is NULL but MMNLSE_KERR_MANAKOV is set");
+  if (manakov && c.precision != MMNLSE_FP32) return bad("the Manakov form runs in FP32 only");
+  if (manakov) {
+    for (size_t i = 0; i < (size_t)M * M; ++i)
+      if (!std::isfinite(c.kappa[i])) return bad("kappa is not finite");
+  }
+  if (!c.S && !manakov) return bad("S is NULL");
   if (!std::isfinite(c.gamma)) return bad("gamma must be finite");
   if (!(c.h_km > 0) || !std::isfinite(c.h_km)) return bad("h must be positive");
   if (!(c.L_km >= 0) || !std::isfinite(c.L_km)) return bad("L must be >= 0");
@@ -223,6 +231,7 @@ mmnlse_status validate_config(const mmnlse_config &c, std::string &why) {
   if (c.alpha)
     for (int i = 0; i < M; ++i)
       if (!std::isfinite(c.alpha[i])) return bad("alpha is not finite");
+  if (manakov) return MMNLSE_OK;
   const size_t n4 = (size_t)M * M * M * M;
   for (size_t i = 0; i < n4; ++i)
     if (!std::isfinite(c.S[i])) return bad("S is not finite");
@@ -241,6 +250,7 @@ void set_last_error(const std::string &msg) { g_err = msg; }
 size_t estimate_plan_bytes(const mmnlse_config &cfg) {
   const size_t M = (size_t)cfg.M, T = (size_t)cfg.T, MT = M * T;
   size_t b = 3 * MT * sizeof(float2) + MT * sizeof(float4) + T * sizeof(float4) + 1024 * sizeof(double2);
+  if (cfg.flags & MMNLSE_KERR_MANAKOV) return b + M * M * sizeof(float);
   const bool sym = (cfg.flags & MMNLSE_S_SYMMETRIC) != 0;
   const bool mfma = cfg.precision == MMNLSE_SPLIT_BF16 ||
                     (!(cfg.flags & MMNLSE_KERR_GENERIC) && cfg.M > 8 && sym);
@@ -305,12 +315,14 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
   // Kerr path
   const bool force_generic = (cfg->flags & MMNLSE_KERR_GENERIC) != 0;
   const char *fpath = std::getenv("MMNLSE_KERR_PATH");
-  if (cfg->precision == MMNLSE_SPLIT_BF16) pl->kerr_path = KERR_MFMA;
+  const bool manakov = (cfg->flags & MMNLSE_KERR_MANAKOV) != 0;
+  if (manakov) pl->kerr_path = KERR_MANAKOV;
+  else if (cfg->precision == MMNLSE_SPLIT_BF16) pl->kerr_path = KERR_MFMA;
   else if (force_generic) pl->kerr_path = KERR_GENERIC;
   else if (M <= 8) pl->kerr_path = KERR_SMALL;
   else if (sym) pl->kerr_path = KERR_MFMA;
   else pl->kerr_path = KERR_GENERIC;
-  if (fpath && !force_generic && cfg->precision == MMNLSE_FP32) {
+  if (fpath && !force_generic && !manakov && cfg->precision == MMNLSE_FP32) {
     const int v = std::atoi(fpath);
     if (v == KERR_SMALL && M <= 8) pl->kerr_path = KERR_SMALL;
     if (v == KERR_GENERIC) pl->kerr_path = KERR_GENERIC;
@@ -339,7 +351,10 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
     if ((e = dev_alloc(*pl, (void **)&pl->E, sizeof(float4) * MT)) != hipSuccess) goto nomem;
     if ((e = hipMemcpy(pl->E, E.data(), sizeof(float4) * MT, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
   }
-  if (pl->kerr_path != KERR_MFMA) {
+  if (pl->kerr_path == KERR_MANAKOV) {
+    if ((e = dev_alloc(*pl, (void **)&pl->kappa, sizeof(float) * M * M)) != hipSuccess) goto nomem;
+    if ((e = hipMemcpy(pl->kappa, cfg->kappa, sizeof(float) * M * M, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
+  } else if (pl->kerr_path != KERR_MFMA) {
     std::vector<float> Sg(n4);
     for (int p = 0; p < M; ++p)
       for (int l = 0; l < M; ++l)

@@ -48,7 +48,7 @@ __device__ __forceinline__ float2 cfma_conj(float2 acc, float2 a, float2 b) {
 // host-side plan
 // ---------------------------------------------------------------------------
 
-enum KerrPath : int32_t { KERR_SMALL = 0, KERR_GENERIC = 1, KERR_MFMA = 2 };
+enum KerrPath : int32_t { KERR_SMALL = 0, KERR_GENERIC = 1, KERR_MFMA = 2, KERR_MANAKOV = 3 };
 
 // Which fields a Kerr launch reads and writes (the RK4 combinations of Eq. 6
 // fused into the kernel's prologue and epilogue).
@@ -96,6 +96,7 @@ struct Plan {
   float4 *E = nullptr;    // [M][T] exp(h/2 L)/T as hi + lo, in the FFT's storage order
   float4 *E2 = nullptr;   // same for step 2h (step doubling), built on first use
   float *Sg = nullptr;    // generic tensor layout [p][n][m][l]
+  float *kappa = nullptr; // Manakov coupling matrix [a][b]
   // packed symmetric tensor (matrix-core path): rows r = (p<=n), cols q = (l<=m)
   int P = 0, Ppad = 0;
   float *Sp = nullptr;          // [Ppad][Ppad] FP32, weight 2 for l<m folded in

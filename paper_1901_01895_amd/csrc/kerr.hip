@@ -22,7 +22,8 @@ namespace {
 struct KArgs {
   const float2 *src0, *src1, *src2;
   float2 *out0, *out1;
-  const float *Sg;  // [p][n][m][l]
+  const float *Sg;     // [p][n][m][l]
+  const float *kappa;  // [a][b] (Manakov form)
   float hg;         // h * gamma
   int M, T, next;
 };
@@ -167,6 +168,92 @@ __global__ __launch_bounds__(TT * GW) void kerr_tiled(KArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Manakov / XPM form of Eq. (1): k_a = i h gamma (sum_b kappa_ab |X_b|^2) X_a.
+// A workgroup stages the intensities |X_b|^2 of 64 samples of all modes in
+// LDS; each wave takes whole modes a (wave-uniform row of kappa through the
+// scalar cache).  Up to 256 modes (two 64 KiB intensity tiles).
+// ---------------------------------------------------------------------------
+template <int STAGE>
+__device__ __forceinline__ float2 stage_arg(const KArgs &a, size_t g) {
+  float2 v = a.src0[g];
+  if (STAGE == STAGE_K2) v = caxpy(v, 0.5f, a.src1[g]);
+  if (STAGE == STAGE_K3) v = caxpy(v, 0.5f, a.src2[g]);
+  return v;
+}
+
+__device__ __forceinline__ float xpm_phase(const KArgs &a, const float *Is, int p, int lane) {
+  const float *__restrict__ k = a.kappa + (size_t)p * a.M;
+  float phi = 0.f;
+  for (int b = 0; b < a.M; ++b) phi = fmaf(k[b], Is[b * TT + lane], phi);
+  return phi;
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(TT * GW) void kerr_manakov(KArgs a) {
+  extern __shared__ float shf[];
+  float *Is = shf;                // |X_b|^2 of the stage argument
+  float *Is2 = shf + a.M * TT;    // |A(z+h)|^2 for the k1 of the next step (K4 only)
+  const int t0 = blockIdx.x * TT;
+  const int lane = threadIdx.x & (TT - 1);
+  const int w = threadIdx.x / TT;
+  for (int idx = threadIdx.x; idx < a.M * TT; idx += TT * GW) {
+    const float2 v = stage_arg<STAGE>(a, (size_t)(idx / TT) * a.T + t0 + (idx % TT));
+    Is[idx] = fmaf(v.x, v.x, v.y * v.y);
+  }
+  __syncthreads();
+  for (int p0 = w; p0 < a.M; p0 += GW) {
+    const int p = __builtin_amdgcn_readfirstlane(p0);
+    const float hphi = a.hg * xpm_phase(a, Is, p, lane);
+    const size_t g = (size_t)p * a.T + t0 + lane;
+    const float2 x = stage_arg<STAGE>(a, g);
+    const float2 k = make_float2(-hphi * x.y, hphi * x.x);
+    if (STAGE == STAGE_PLAIN || STAGE == STAGE_K2) {
+      a.out0[g] = k;
+    } else if (STAGE == STAGE_K3) {
+      const float2 ai = a.src0[g], k1 = a.src1[g], k2 = a.src2[g];
+      a.out0[g] = cadd(ai, k);
+      float2 z = caxpy(ai, 1.f / 6.f, k1);
+      z = caxpy(z, 1.f / 3.f, k2);
+      a.out1[g] = caxpy(z, 1.f / 3.f, k);
+    } else {
+      const float2 An = caxpy(a.src1[g], 1.f / 6.f, k);
+      a.out0[g] = An;
+      Is2[p * TT + lane] = fmaf(An.x, An.x, An.y * An.y);
+    }
+  }
+  if (STAGE == STAGE_K4 && a.next) {
+    __syncthreads();
+    for (int p0 = w; p0 < a.M; p0 += GW) {
+      const int p = __builtin_amdgcn_readfirstlane(p0);
+      const float hphi = a.hg * xpm_phase(a, Is2, p, lane);
+      const size_t g = (size_t)p * a.T + t0 + lane;
+      const float2 An = a.out0[g];  // written by this thread above
+      a.out1[g] = make_float2(-hphi * An.y, hphi * An.x);
+    }
+  }
+}
+
+hipError_t go_manakov(const KArgs &a, KerrStage st, hipStream_t s) {
+  dim3 grid(a.T / TT);
+  const size_t shm = (size_t)(st == STAGE_K4 ? 2 : 1) * a.M * TT * sizeof(float);
+  auto launch = [&](auto kern) -> hipError_t {
+    if (shm > 65536) {
+      hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, grid, dim3(TT * GW), shm, s, a);
+    return hipGetLastError();
+  };
+  switch (st) {
+    case STAGE_PLAIN: return launch(kerr_manakov<STAGE_PLAIN>);
+    case STAGE_K2: return launch(kerr_manakov<STAGE_K2>);
+    case STAGE_K3: return launch(kerr_manakov<STAGE_K3>);
+    case STAGE_K4: return launch(kerr_manakov<STAGE_K4>);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int M>
 hipError_t go_small(const KArgs &a, KerrStage st, hipStream_t s) {
   dim3 grid((a.T + 255) / 256);
@@ -215,10 +302,12 @@ hipError_t launch_kerr(const Plan &pl, double h, const KerrLaunch &k) {
   a.out0 = k.out0;
   a.out1 = k.out1;
   a.Sg = pl.Sg;
+  a.kappa = pl.kappa;
   a.hg = (float)(h * pl.gamma);
   a.M = pl.M;
   a.T = pl.T;
   a.next = k.next;
+  if (pl.kerr_path == KERR_MANAKOV) return go_manakov(a, k.stage, pl.stream);
   if (pl.kerr_path == KERR_SMALL) {
     switch (pl.M) {
       case 1: return go_small<1>(a, k.stage, pl.stream);

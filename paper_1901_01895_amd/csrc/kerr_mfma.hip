@@ -21,6 +21,7 @@
 // v_mfma_f32_32x32x16_bf16, accumulated in FP32 (the lo*lo term, 2^-16 of
 // the product, is dropped).
 
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -41,9 +42,6 @@ struct MArgs {
   float hg;
   int M, T, P, Ppad, next;
 };
-
-constexpr int RT_F32 = 4;   // row tiles per pass (B formed once per pass)
-constexpr int RT_BF16 = 4;
 
 // Output row of accumulator register v for lane-half `half` of a 32x32 tile.
 __device__ __forceinline__ int acc_row(int v, int half) { return 8 * (v >> 2) + 4 * half + (v & 3); }
@@ -87,16 +85,16 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
     cim[j] = floatx16{0};
   }
   if (!SPLIT) {
-    // 4 k-steps of 2 per group; Ppad is a multiple of 32, so the number of
-    // groups is even and the ping-pong below needs no tail
-    const int nk = a.Ppad / 8;
+    const int nk = a.Ppad / 8;  // 4 k-steps of 2 per iteration
     const float4 *Ab = a.A32 + (size_t)rt0 * nk * 64 + lane;
-    float4 a0[RT], a1[RT];
-    auto load = [&](float4 (&dst)[RT], int kq) {
+    float4 av[RT], an[RT];
 #pragma unroll
-      for (int j = 0; j < RT; ++j) dst[j] = Ab[((size_t)j * nk + kq) * 64];
-    };
-    auto group = [&](const float4 (&av)[RT], int kq) {
+    for (int j = 0; j < RT; ++j) av[j] = Ab[(size_t)j * nk * 64];
+    for (int kq = 0; kq < nk; ++kq) {
+      if (kq + 1 < nk) {
+#pragma unroll
+        for (int j = 0; j < RT; ++j) an[j] = Ab[((size_t)j * nk + kq + 1) * 64];
+      }
       const int4 p0 = *(const int4 *)(a.pairs + 8 * kq);
       const int4 p1 = *(const int4 *)(a.pairs + 8 * kq + 4);
 #pragma unroll
@@ -115,27 +113,27 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
           cim[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, bim, cim[j], 0, 0, 0);
         }
       }
-    };
-    load(a0, 0);
-    for (int kq = 0; kq < nk; kq += 2) {
-      load(a1, kq + 1);
-      group(a0, kq);
-      if (kq + 2 < nk) load(a0, kq + 2);
-      group(a1, kq + 1);
+#pragma unroll
+      for (int j = 0; j < RT; ++j) av[j] = an[j];
     }
   } else {
-    const int nk = a.Ppad / 16;  // k-steps of 16; even, see above
+    const int nk = a.Ppad / 16;  // k-steps of 16
     const uint4 *Hb = a.Ah + (size_t)rt0 * nk * 64 + lane;
     const uint4 *Lb = a.Al + (size_t)rt0 * nk * 64 + lane;
-    uint4 h0[RT], l0[RT], h1[RT], l1[RT];
-    auto load = [&](uint4 (&hd)[RT], uint4 (&ld)[RT], int ks) {
+    uint4 ah[RT], al[RT], ahn[RT], aln[RT];
 #pragma unroll
-      for (int j = 0; j < RT; ++j) {
-        hd[j] = Hb[((size_t)j * nk + ks) * 64];
-        ld[j] = Lb[((size_t)j * nk + ks) * 64];
+    for (int j = 0; j < RT; ++j) {
+      ah[j] = Hb[(size_t)j * nk * 64];
+      al[j] = Lb[(size_t)j * nk * 64];
+    }
+    for (int ks = 0; ks < nk; ++ks) {
+      if (ks + 1 < nk) {
+#pragma unroll
+        for (int j = 0; j < RT; ++j) {
+          ahn[j] = Hb[((size_t)j * nk + ks + 1) * 64];
+          aln[j] = Lb[((size_t)j * nk + ks + 1) * 64];
+        }
       }
-    };
-    auto step = [&](const uint4 (&ah)[RT], const uint4 (&al)[RT], int ks) {
       const int *pp = a.pairs + 16 * ks + 8 * half;
       bf16x8 rh, rl, ih, il;
 #pragma unroll
@@ -162,59 +160,68 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
         cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, il, cim[j], 0, 0, 0);
         cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, ih, cim[j], 0, 0, 0);
       }
-    };
-    load(h0, l0, 0);
-    for (int ks = 0; ks < nk; ks += 2) {
-      load(h1, l1, ks + 1);
-      step(h0, l0, ks);
-      if (ks + 2 < nk) load(h0, l0, ks + 2);
-      step(h1, l1, ks + 1);
+#pragma unroll
+      for (int j = 0; j < RT; ++j) {
+        ah[j] = ahn[j];
+        al[j] = aln[j];
+      }
     }
   }
 #pragma unroll
   for (int j = 0; j < RT; ++j) scatter_tile<TT>(a, cre[j], cim[j], rt0 + j, Xs, Os, lane, col);
 }
 
-// Full contraction: row tiles in passes of RT_MAX, the remainder in passes
-// of 2 and 1 (rows are padded to a multiple of 32 only).
-template <int W, bool SPLIT>
-__device__ __forceinline__ void contract(const MArgs &a, const float2 *Xs, float2 *Os, int lane, int col) {
-  constexpr int RTM = SPLIT ? RT_BF16 : RT_F32;
+// Full contraction for one wave: the row tiles are cut into passes of RTM
+// (remainder in passes of 2 and 1; rows are padded to a multiple of 32 only)
+// and pass i belongs to row group i % R.
+template <int W, int R, bool SPLIT, int RTM>
+__device__ __forceinline__ void contract(const MArgs &a, const float2 *Xs, float2 *Os, int lane, int col,
+                                         int rg) {
   const int nrt = a.Ppad / 32;
-  int rt0 = 0;
-  for (; rt0 + RTM <= nrt; rt0 += RTM) contract_pass<W, RTM, SPLIT>(a, Xs, Os, lane, col, rt0);
+  int rt0 = 0, unit = 0;
+  for (; rt0 + RTM <= nrt; rt0 += RTM, ++unit)
+    if (unit % R == rg) contract_pass<W, RTM, SPLIT>(a, Xs, Os, lane, col, rt0);
   if (RTM > 2 && rt0 + 2 <= nrt) {
-    contract_pass<W, 2, SPLIT>(a, Xs, Os, lane, col, rt0);
+    if (unit % R == rg) contract_pass<W, 2, SPLIT>(a, Xs, Os, lane, col, rt0);
     rt0 += 2;
+    ++unit;
   }
-  if (rt0 < nrt) contract_pass<W, 1, SPLIT>(a, Xs, Os, lane, col, rt0);
+  if (rt0 < nrt && unit % R == rg) contract_pass<W, 1, SPLIT>(a, Xs, Os, lane, col, rt0);
 }
 
-template <int W, bool SPLIT, int STAGE>
-__global__ __launch_bounds__(64 * W) void kerr_mfma(MArgs a) {
+// Workgroup = W column groups x R row groups of waves.  Wave w owns the 32
+// samples of column group w % W and the passes of row group w / W, and
+// scatters into that row group's partial tile; the R partials are summed in
+// a fixed order, so the result does not depend on timing.
+template <int W, int R, bool SPLIT, int RTM, int STAGE>
+__global__ __launch_bounds__(64 * W * R) void kerr_mfma(MArgs a) {
   constexpr int TT = 32 * W;
-  constexpr int NT = 64 * W;
+  constexpr int NT = 64 * W * R;
   extern __shared__ float2 sh[];
+  const int MT = a.M * TT;
   float2 *Xs = sh;
-  float2 *Os = sh + a.M * TT;
+  float2 *Os = sh + MT;  // R partial tiles
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int col = 32 * w + (lane & 31);
+  const int cg = w % W, rg = w / W;
+  const int col = 32 * cg + (lane & 31);
   const int t0 = blockIdx.x * TT;
-  for (int idx = threadIdx.x; idx < a.M * TT; idx += NT) {
+  for (int idx = threadIdx.x; idx < MT; idx += NT) {
     const size_t g = (size_t)(idx / TT) * a.T + t0 + (idx % TT);
     float2 v = a.src0[g];
     if (STAGE == STAGE_K2) v = caxpy(v, 0.5f, a.src1[g]);
     if (STAGE == STAGE_K3) v = caxpy(v, 0.5f, a.src2[g]);
     Xs[idx] = v;
-    Os[idx] = make_float2(0.f, 0.f);
   }
+  for (int idx = threadIdx.x; idx < R * MT; idx += NT) Os[idx] = make_float2(0.f, 0.f);
   __syncthreads();
-  contract<W, SPLIT>(a, Xs, Os, lane, col);
+  contract<W, R, SPLIT, RTM>(a, Xs, Os + rg * MT, lane, col, rg);
   __syncthreads();
-  for (int idx = threadIdx.x; idx < a.M * TT; idx += NT) {
+  for (int idx = threadIdx.x; idx < MT; idx += NT) {
     const size_t g = (size_t)(idx / TT) * a.T + t0 + (idx % TT);
-    const float2 o = Os[idx];
+    float2 o = Os[idx];
+#pragma unroll
+    for (int r = 1; r < R; ++r) o = cadd(o, Os[r * MT + idx]);
     const float2 k = make_float2(-a.hg * o.y, a.hg * o.x);  // i h gamma sum
     if (STAGE == STAGE_PLAIN || STAGE == STAGE_K2) {
       a.out0[g] = k;
@@ -228,25 +235,28 @@ __global__ __launch_bounds__(64 * W) void kerr_mfma(MArgs a) {
       const float2 An = caxpy(a.src1[g], 1.f / 6.f, k);
       a.out0[g] = An;
       Xs[idx] = An;
-      Os[idx] = make_float2(0.f, 0.f);
     }
   }
   if (STAGE == STAGE_K4 && a.next) {
     __syncthreads();
-    contract<W, SPLIT>(a, Xs, Os, lane, col);
+    for (int idx = threadIdx.x; idx < R * MT; idx += NT) Os[idx] = make_float2(0.f, 0.f);
     __syncthreads();
-    for (int idx = threadIdx.x; idx < a.M * TT; idx += NT) {
-      const float2 o = Os[idx];
+    contract<W, R, SPLIT, RTM>(a, Xs, Os + rg * MT, lane, col, rg);
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < MT; idx += NT) {
+      float2 o = Os[idx];
+#pragma unroll
+      for (int r = 1; r < R; ++r) o = cadd(o, Os[r * MT + idx]);
       a.out1[(size_t)(idx / TT) * a.T + t0 + (idx % TT)] = make_float2(-a.hg * o.y, a.hg * o.x);
     }
   }
 }
 
-template <int W, bool SPLIT>
+template <int W, int R, bool SPLIT, int RTM>
 hipError_t go(const MArgs &a, KerrStage st, hipStream_t s) {
   constexpr int TT = 32 * W;
-  const dim3 grid(a.T / TT), block(64 * W);
-  const size_t shm = (size_t)2 * a.M * TT * sizeof(float2);
+  const dim3 grid(a.T / TT), block(64 * W * R);
+  const size_t shm = (size_t)(1 + R) * a.M * TT * sizeof(float2);
   auto launch = [&](auto kern) -> hipError_t {
     if (shm > 65536) {
       hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -256,19 +266,38 @@ hipError_t go(const MArgs &a, KerrStage st, hipStream_t s) {
     return hipGetLastError();
   };
   switch (st) {
-    case STAGE_PLAIN: return launch(kerr_mfma<W, SPLIT, STAGE_PLAIN>);
-    case STAGE_K2: return launch(kerr_mfma<W, SPLIT, STAGE_K2>);
-    case STAGE_K3: return launch(kerr_mfma<W, SPLIT, STAGE_K3>);
-    case STAGE_K4: return launch(kerr_mfma<W, SPLIT, STAGE_K4>);
+    case STAGE_PLAIN: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_PLAIN>);
+    case STAGE_K2: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K2>);
+    case STAGE_K3: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K3>);
+    case STAGE_K4: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K4>);
   }
   return hipErrorInvalidValue;
 }
 
+// Workgroup shape by mode count (LDS holds the field tile and R partials,
+// (1 + R) * M * 32W * 8 bytes <= 160 KiB):
+//   M <= 64: 4 column groups (128 samples), 1 row group
+//   M <= 125: 1 column group (32 samples), 4 row groups
+//   M <= 208: 1 x 2;   M <= 256: 1 x 1
+template <bool SPLIT, int RTM>
+hipError_t go_shape(const MArgs &a, KerrStage st, hipStream_t s) {
+  if (a.M <= 64 && a.T % 128 == 0) return go<4, 1, SPLIT, RTM>(a, st, s);
+  if (a.M <= 125) return go<1, 4, SPLIT, RTM>(a, st, s);
+  if (a.M <= 208) return go<1, 2, SPLIT, RTM>(a, st, s);
+  return go<1, 1, SPLIT, RTM>(a, st, s);
+}
+
 template <bool SPLIT>
 hipError_t go_w(const MArgs &a, KerrStage st, hipStream_t s) {
-  if (a.M <= 64 && a.T % 128 == 0) return go<4, SPLIT>(a, st, s);
-  if (a.M <= 128) return go<2, SPLIT>(a, st, s);
-  return go<1, SPLIT>(a, st, s);
+  // row tiles per pass: each pass forms B once and keeps 2*RTM accumulator
+  // tiles; MMNLSE_MFMA_RT (2 or 4) overrides the default for tuning runs
+  static const int rt_env = [] {
+    const char *e = std::getenv("MMNLSE_MFMA_RT");
+    return e ? std::atoi(e) : 0;
+  }();
+  const int rtm = rt_env == 2 || rt_env == 4 ? rt_env : 2;
+  if (rtm == 4) return go_shape<SPLIT, 4>(a, st, s);
+  return go_shape<SPLIT, 2>(a, st, s);
 }
 
 uint16_t bf16_bits(float x) {  // round to nearest even

@@ -217,3 +217,39 @@ def test_step_doubling_estimate(gpu_lib):
     d_orc, _ = oracle.step_doubling_estimate(p.A0, p.beta, None, p.S, p.gamma, p.dt, p.h)
     assert abs(d_gpu / d_orc - 1) < 1e-2
     P.close()
+
+
+@pytest.mark.parametrize("M", [1, 5, 40, 240])
+def test_kerr_manakov(gpu_lib, M):
+    """The paper's Eq. (1) nonlinear operator on the GPU vs the FP64 oracle."""
+    mm = gpu_lib
+    T = 512
+    rng = np.random.default_rng((15, M))
+    kappa = W.xpm_matrix(M, rng)
+    beta = np.zeros((M, 1))
+    P = mm.Propagator(M, T, 0.5, beta, None, 1.3, 0.05, 0.05, kappa=kappa)
+    assert P.kerr_path == "manakov"
+    X = crandn(rng, M, T)
+    Y = host(P.kerr(dev(X)))
+    ref = 0.05 * oracle.KerrManakov(kappa.astype(np.float64), 1.3)(X.astype(np.complex128))
+    assert rel(Y, ref) < 2e-6
+    P.close()
+
+
+def test_manakov_propagation(gpu_lib):
+    """Whole RK4IP propagation with the paper's Eq. (1) model (30 rows = 15 spatial modes
+    x 2 polarizations, attenuation on) vs the oracle."""
+    mm = gpu_lib
+    p = W.manakov_problem(M=30, T=2 ** 12, n_steps=20)
+    print(f"propagate manakov M={p.M} T={p.T} steps={p.n_steps}", flush=True)
+    P = mm.Propagator.from_problem(p)
+    assert P.kerr_path == "manakov"
+    out, st = P.propagate(p.A0, stats=True)
+    ref = oracle.propagate(p.A0, p.beta, p.alpha, None, p.gamma, p.dt, p.h, p.n_steps,
+                           kerr=oracle.KerrManakov(p.kappa.astype(np.float64), p.gamma))
+    err = rel(out, ref)
+    print(f"  rel L2 = {err:.3e}", flush=True)
+    assert err < 1e-5
+    # attenuation: power decays as exp(-alpha L) exactly (the Kerr term conserves it)
+    assert abs(st["power_out"] / st["power_in"] / np.exp(-p.alpha[0] * p.L) - 1) < 1e-5
+    P.close()

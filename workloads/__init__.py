@@ -21,4 +21,6 @@ from .fiber import (  # noqa: F401
     request_problem,
     RequestSpec,
     table3_beta,
+    manakov_problem,
+    xpm_matrix,
 )

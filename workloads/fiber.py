@@ -73,6 +73,7 @@ class Problem:
     n_steps: int
     symmetric: bool           # S invariant under every index permutation
     meta: dict = field(default_factory=dict)
+    kappa: np.ndarray | None = None   # [M, M] float32: Manakov / XPM form (S unused)
 
     @property
     def M(self) -> int:
@@ -313,6 +314,29 @@ def make_problem(name: str, T: int | None = None, n_steps: int | None = None,
         return Problem(name, A.astype(np.complex64), table3_beta(M), np.zeros(M), S, 0.5,
                        dt, 0.02, n_steps or 500, True, info)
     raise ValueError(f"unknown workload {name!r}")
+
+
+def xpm_matrix(M: int, rng: np.random.Generator) -> np.ndarray:
+    """Synthetic symmetric XPM coupling matrix: kappa_aa = 1 (intramodal),
+    kappa_ab ~ U(0.2, 0.7) for a != b (intermodal), FP32."""
+    k = rng.uniform(0.2, 0.7, (M, M))
+    k = np.triu(k, 1)
+    k = k + k.T + np.eye(M)
+    return k.astype(np.float32)
+
+
+def manakov_problem(M: int = 30, T: int = 2 ** 14, n_steps: int = 100, cfg: int = 5) -> Problem:
+    """The paper's own model (Eq. 1, Manakov / XPM form): M rows (spatial modes x 2
+    polarizations), 8-channel 16-QAM WDM per row at -2 dBm/channel, 32 samples per
+    symbol, beta from Table 3 per mode group (two rows per spatial mode), the
+    paper's attenuation 0.23 dB/km and gamma = 0.61 /W/km, h = 100 m."""
+    A, dt = shaped_field(_rng(cfg, STREAM_SYMBOLS), M, T, 32, 8, 0.05, "16qam", _dbm(-2.0))
+    spatial = (M + 1) // 2
+    beta = np.repeat(table3_beta(spatial), 2, axis=0)[:M]
+    alpha = np.full(M, 0.23 * math.log(10.0) / 10.0)   # dB/km -> 1/km (power)
+    kappa = xpm_matrix(M, _rng(cfg, STREAM_S))
+    return Problem("manakov", A.astype(np.complex64), beta, alpha, None, 0.61, dt, 0.1, n_steps,
+                   False, {"model": "Eq. (1) Manakov/XPM"}, kappa)
 
 
 # ----------------------------------------------------------------------------
