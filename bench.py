@@ -136,7 +136,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="wdm36", choices=sorted(WORKLOADS) + ["serving"])
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"],
+                    help="precision of the headline value; the other one is reported beside it")
+    ap.add_argument("--precision-only", action="store_true", help="measure only --precision")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--requests", type=int, default=256, help="serving: number of requests")
@@ -162,7 +164,50 @@ def main():
         print(json.dumps(serving(args)), flush=True)
         return
     p = W.make_problem(args.workload)
-    prec = mm.FP32 if args.precision == "fp32" else mm.SPLIT_BF16
+    precs = [args.precision] if args.precision_only else \
+        [args.precision] + [q for q in ("fp32", "split_bf16") if q != args.precision]
+    runs = {}
+    for q in precs:
+        if q == "split_bf16" and not p.symmetric:
+            continue
+        runs[q] = measure(mm, W, p, q, args)
+    main_run = runs[args.precision]
+    out = {
+        "metric": METRIC, "value": main_run["value"], "unit": "mode*sample*steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "bf16x3-split/f32-acc", "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.workload], "M": p.M, "T": p.T, "h_km": p.h,
+                   "precision": args.precision, "kerr_kernel": main_run["kerr_kernel"]},
+        "roofline": main_run["roofline"],
+        "kernels": main_run["kernels"],
+    }
+    for q, r in runs.items():
+        if q != args.precision:
+            out[q] = {k: r[k] for k in ("value", "ms_per_step", "roofline", "kernels")}
+            out[q]["speedup_vs_" + args.precision] = r["value"] / main_run["value"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def traffic_for(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1901_01895_amd", "csrc", rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
+def measure(mm, W, p, precision: str, args) -> dict:
+    import torch
+    prec = mm.FP32 if precision == "fp32" else mm.SPLIT_BF16
     P = mm.Propagator.from_problem(p, precision=prec)
     A0 = torch.from_numpy(p.A0.astype(np.complex64)).cuda()
     A = A0.clone()
@@ -199,30 +244,21 @@ def main():
             bound, peak = "mfma", FP32_PEAK_TFLOPS
         else:
             bound, peak = "alu", FP32_PEAK_TFLOPS
+        kname = f"kerr_{path}_{precision}"
         roof = {"bound": bound, "achieved": kerr_tflops, "peak": peak, "unit": "TFLOP/s",
-                "frac": kerr_tflops / peak, "traffic": None, "kernel": f"kerr_{path}",
-                "avg_launch_ms": kerr_avg_ms}
+                "frac": kerr_tflops / peak, "traffic": traffic_for(kname, args.workload),
+                "kernel": kname, "avg_launch_ms": kerr_avg_ms,
+                "evals_per_launch": evals_per_launch}
     else:
+        kname = "linear_half_step"
         roof = {"bound": "hbm", "achieved": lin_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": lin_gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "linear_half_step",
-                "avg_launch_ms": lin_avg_ms}
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "mode*sample*steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if prec == mm.FP32 else "bf16x3-split/f32-acc", "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload], "M": p.M, "T": p.T, "h_km": p.h,
-                   "precision": args.precision, "kerr_kernel": path},
-        "roofline": roof,
-        "kernels": {"kerr_ms_per_step": prof["kerr_ms"] / args.steps,
-                    "linear_ms_per_step": prof["linear_ms"] / args.steps,
-                    "kerr_tflops": kerr_tflops, "linear_GBps": lin_gbs},
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+                "frac": lin_gbs / HBM_PEAK_GBS, "traffic": traffic_for(kname, args.workload),
+                "kernel": kname, "avg_launch_ms": lin_avg_ms}
     P.close()
-    print(json.dumps(out), flush=True)
+    return {"value": value, "ms_per_step": ms_per_step, "roofline": roof, "kerr_kernel": path,
+            "kernels": {"kerr_ms_per_step": prof["kerr_ms"] / args.steps,
+                        "linear_ms_per_step": prof["linear_ms"] / args.steps,
+                        "kerr_tflops": kerr_tflops, "linear_GBps": lin_gbs}}
 
 
 if __name__ == "__main__":
