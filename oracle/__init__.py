@@ -21,6 +21,7 @@ from .rk4ip import (  # noqa: F401
     power,
     propagate,
     rk4ip_step,
+    ssfm_rk4_step,
     step_doubling_estimate,
     time_grid,
 )

@@ -36,7 +36,9 @@ Pins (tests/test_oracle_pins.py, all CPU):
 * fundamental soliton and 4th-order convergence under step halving;
 * packed symmetric Kerr == generic Kerr for symmetric S;
 * Manakov/XPM form of Eq. (1): exact per-mode phase rotation without
-  dispersion, and equality with the tensor form S_plmn = kappa_pm d_lp d_mn.
+  dispersion, and equality with the tensor form S_plmn = kappa_pm d_lp d_mn;
+* SSFM-RK4 (Eq. 4): exact for the linear part, identical to RK4IP without
+  dispersion, second order on the soliton.
 
 Units: t in ps, z in km, power in W, w in rad/ps, beta_n in ps^n/km.
 """
@@ -50,7 +52,7 @@ import numpy as np
 __all__ = [
     "time_grid", "angular_frequencies", "linear_operator", "half_step_propagator",
     "apply_linear", "KerrGeneric", "KerrPacked", "KerrManakov", "kerr_term", "rk4ip_step",
-    "propagate", "power", "step_doubling_estimate",
+    "propagate", "power", "step_doubling_estimate", "ssfm_rk4_step",
 ]
 
 
@@ -210,6 +212,19 @@ def rk4ip_step(A: np.ndarray, E: np.ndarray, h: float, N) -> np.ndarray:
     return apply_linear(AI + k1 / 6.0 + k2 / 3.0 + k3 / 3.0, E) + k4 / 6.0   # (6f)
 
 
+def ssfm_rk4_step(A: np.ndarray, E: np.ndarray, h: float, N) -> np.ndarray:
+    """Symmetric split-step of Eq. (4): a half linear step, the nonlinear part
+    over h (A' = N(A), classical fourth-order Runge-Kutta: the paper's
+    SSFM-RK4 variant), another half linear step.  Global error O(h^2)."""
+    X = apply_linear(A, E)
+    k1 = h * N(X)
+    k2 = h * N(X + k1 / 2.0)
+    k3 = h * N(X + k2 / 2.0)
+    k4 = h * N(X + k3)
+    X = X + (k1 + 2.0 * k2 + 2.0 * k3 + k4) / 6.0
+    return apply_linear(X, E)
+
+
 def _kerr_for(S, gamma, kerr):
     if kerr is not None and not isinstance(kerr, str):
         return kerr
@@ -221,19 +236,26 @@ def _kerr_for(S, gamma, kerr):
 
 def propagate(A0: np.ndarray, beta: np.ndarray, alpha: np.ndarray | None, S: np.ndarray,
               gamma: float, dt: float, h: float, n_steps: int, kerr=None,
-              callback=None) -> np.ndarray:
-    """n_steps fixed RK4IP steps of size h from A0 (promoted to complex128).
+              callback=None, method: str = "rk4ip") -> np.ndarray:
+    """n_steps fixed steps of size h from A0 (promoted to complex128).
 
-    ``kerr`` may be None/"generic", "packed" (S must be symmetric in (l,m) and
-    (p,n)), or a ready callable.  ``callback(step, A)`` is called after each
-    step when given.
+    ``method`` is "rk4ip" (Eq. 6, default) or "ssfm_rk4" (Eq. 4 with an RK4
+    nonlinear step).  ``kerr`` may be None/"generic", "packed" (S must be
+    symmetric in (l,m) and (p,n)), or a ready callable.  ``callback(step, A)``
+    is called after each step when given.
     """
     A = np.array(A0, dtype=np.complex128, copy=True)
     M, T = A.shape
     E = half_step_propagator(angular_frequencies(T, dt), beta, alpha, h)
     N = _kerr_for(S, gamma, kerr)
+    if method == "rk4ip":
+        step = rk4ip_step
+    elif method == "ssfm_rk4":
+        step = ssfm_rk4_step
+    else:
+        raise ValueError(method)
     for s in range(n_steps):
-        A = rk4ip_step(A, E, h, N)
+        A = step(A, E, h, N)
         if callback is not None:
             callback(s + 1, A)
     return A

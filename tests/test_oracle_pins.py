@@ -327,6 +327,48 @@ def test_manakov_single_mode_is_spm():
 
 
 # ----------------------------------------------------------------------------
+# symmetric split-step with an RK4 nonlinear step (Eq. 4, SSFM-RK4)
+# ----------------------------------------------------------------------------
+
+def test_ssfm_linear_part_exact():
+    """N = 0: two half steps per step give exp(h L) exactly (GVD closed form)."""
+    T, dt, T0, b2, z = 8192, 0.05, 3.0, -20.0, 0.7
+    t = oracle.time_grid(T, dt)
+    A0 = np.exp(-t ** 2 / (2 * T0 ** 2))[None, :]
+    out = oracle.propagate(A0, np.array([[0.0, 0.0, b2]]), None, np.zeros((1, 1, 1, 1)), 0.0,
+                           dt, z / 35, 35, method="ssfm_rk4")
+    c = T0 ** 2 - 1j * b2 * z
+    assert _rel(out[0], T0 / np.sqrt(c) * np.exp(-t ** 2 / (2 * c))) < 1e-12
+
+
+def test_ssfm_equals_rk4ip_without_dispersion():
+    rng = _rng(23)
+    M = 3
+    S = symmetric_gaussian_tensor(M, rng)
+    A0 = _crandn(rng, M, 32)
+    a = oracle.propagate(A0, np.zeros((M, 1)), None, S, 1.2, 1.0, 0.02, 10, method="ssfm_rk4")
+    b = oracle.propagate(A0, np.zeros((M, 1)), None, S, 1.2, 1.0, 0.02, 10)
+    assert _rel(a, b) < 1e-13
+
+
+def test_ssfm_is_second_order_and_less_accurate_than_rk4ip():
+    """Eq. (4) has a global error O(h^2) (splitting error), RK4IP O(h^4): on the
+    fundamental soliton the SSFM error falls ~4x per step halving and stays far
+    above RK4IP's at the same h."""
+    errs = []
+    for h, n in ((0.02, 50), (0.01, 100)):
+        p = soliton_problem(noise=0.0, h=h, n_steps=n)
+        out = oracle.propagate(p.A0, p.beta, None, p.S, p.gamma, p.dt, p.h, p.n_steps, method="ssfm_rk4")
+        t = oracle.time_grid(p.T, p.dt)
+        P0, T0 = p.meta["P0"], p.meta["T0"]
+        exact = math.sqrt(P0) / np.cosh(t / T0) * np.exp(0.5j * p.gamma * P0 * h * n)
+        errs.append(_rel(out[0], exact))
+    assert 3.5 < errs[0] / errs[1] < 4.5
+    e_rk4ip, _, _ = _soliton_error(0.01, 100)
+    assert errs[1] > 20 * e_rk4ip
+
+
+# ----------------------------------------------------------------------------
 # mutants: plausible mistakes planted in a copy of the oracle must fail a pin
 # ----------------------------------------------------------------------------
 
