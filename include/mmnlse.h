@@ -60,6 +60,13 @@ typedef enum {
 
 typedef enum { MMNLSE_C64 = 0, MMNLSE_C128 = 1 } mmnlse_dtype;
 
+/* Stepping method.  RK4IP is the paper's method, Eq. (6a-f); SSFM_RK4 is the
+ * symmetric split-step of Eq. (4) with the nonlinear part integrated over h
+ * by classical RK4 (the paper's "SSFM-RK4" variant, Section 3.1): half a
+ * linear step, four Kerr evaluations, half a linear step (consecutive half
+ * steps inside one call are applied as one full step). */
+typedef enum { MMNLSE_RK4IP = 0, MMNLSE_SSFM_RK4 = 1 } mmnlse_method;
+
 /* S is symmetric in (l,m) and in (p,n): S_plmn == S_pmln == S_nlmp (checked to
  * 1e-6 relative at create).  Enables the packed contraction over the
  * P = M(M+1)/2 pairs.  Every tensor symmetric under all index permutations
@@ -90,6 +97,7 @@ typedef struct {
   uint32_t flags;        /* MMNLSE_S_SYMMETRIC | MMNLSE_KERR_GENERIC | MMNLSE_KERR_MANAKOV */
   const float *kappa;    /* [M][M] host array (row a, column b), used with
                             MMNLSE_KERR_MANAKOV, else ignored; copied */
+  int32_t method;        /* mmnlse_method (0 = RK4IP) */
 } mmnlse_config;
 
 typedef struct {
@@ -149,7 +157,8 @@ mmnlse_status mmnlse_kerr(mmnlse_t h, const void *X, void *Y);
  * Eq. (1) for alpha = 0 and a tensor with S_plmn == S_lpnm. */
 mmnlse_status mmnlse_power(mmnlse_t h, const void *X, double *out);
 
-/* Step-doubling local error estimate (Richardson): from device field X,
+/* Step-doubling local error estimate (Richardson), RK4IP plans only
+ * (E_UNSUPPORTED otherwise): from device field X,
  * takes two RK4IP steps of h and one step of 2h, and writes
  * delta = ||fine - coarse|| / ||fine|| computed in FP64 to *delta (host).
  * The error of the fine result is about delta/15 (fourth order, Section

@@ -17,6 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmmnlse.so")
 
 FP32, SPLIT_BF16 = 0, 1
+RK4IP, SSFM_RK4 = 0, 1
 C64, C128 = 0, 1
 S_SYMMETRIC, KERR_GENERIC, KERR_MANAKOV = 0x1, 0x2, 0x4
 KERR_PATHS = {0: "small", 1: "tiled", 2: "mfma", 3: "manakov"}
@@ -46,7 +47,7 @@ class Config(ctypes.Structure):
         ("alpha", ctypes.POINTER(ctypes.c_double)), ("S", ctypes.POINTER(ctypes.c_float)),
         ("gamma", ctypes.c_double), ("h_km", ctypes.c_double), ("L_km", ctypes.c_double),
         ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
-        ("kappa", ctypes.POINTER(ctypes.c_float)),
+        ("kappa", ctypes.POINTER(ctypes.c_float)), ("method", ctypes.c_int32),
     ]
 
 
@@ -120,7 +121,7 @@ def _dptr(x) -> int:
 
 
 def make_config(M, T, dt, beta, S, gamma, h, L, alpha=None, precision=FP32, symmetric=None,
-                generic=False, kappa=None):
+                generic=False, kappa=None, method=RK4IP):
     """mmnlse_config for the arguments; returns (config, arrays it points into).
 
     With ``kappa`` ([M, M]) the paper's Manakov / XPM nonlinear operator of
@@ -143,16 +144,17 @@ def make_config(M, T, dt, beta, S, gamma, h, L, alpha=None, precision=FP32, symm
     cfg.kappa = kappa.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if kappa is not None else None
     cfg.gamma, cfg.h_km, cfg.L_km = float(gamma), float(h), float(L)
     cfg.precision = int(precision)
+    cfg.method = int(method)
     cfg.flags = ((S_SYMMETRIC if symmetric else 0) | (KERR_GENERIC if generic else 0)
                  | (KERR_MANAKOV if kappa is not None else 0))
     return cfg, (beta, S, alpha, kappa)
 
 
-def problem_config(p, precision=FP32, generic=False, L=None):
+def problem_config(p, precision=FP32, generic=False, L=None, method=RK4IP):
     """mmnlse_config for a workloads.Problem."""
     return make_config(p.M, p.T, p.dt, p.beta, p.S, p.gamma, p.h, p.L if L is None else L,
                        p.alpha if np.any(p.alpha) else None, precision, p.symmetric, generic,
-                       getattr(p, "kappa", None))
+                       getattr(p, "kappa", None), method)
 
 
 class Propagator:
@@ -164,11 +166,11 @@ class Propagator:
 
     def __init__(self, M: int, T: int, dt: float, beta, S, gamma: float, h: float, L: float,
                  alpha=None, precision: int = FP32, symmetric: bool | None = None,
-                 generic: bool = False, stream=None, kappa=None):
+                 generic: bool = False, stream=None, kappa=None, method: int = RK4IP):
         import torch
         lib = load()
         cfg, self._keep = make_config(M, T, dt, beta, S, gamma, h, L, alpha, precision, symmetric, generic,
-                                      kappa)
+                                      kappa, method)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = ctypes.c_void_p()
         _check(lib.mmnlse_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
@@ -180,11 +182,11 @@ class Propagator:
 
     @classmethod
     def from_problem(cls, p, precision: int = FP32, generic: bool = False, L: float | None = None,
-                     stream=None):
+                     stream=None, method: int = RK4IP):
         return cls(p.M, p.T, p.dt, p.beta, p.S, p.gamma, p.h, p.L if L is None else L,
                    alpha=p.alpha if np.any(p.alpha) else None, precision=precision,
                    symmetric=p.symmetric, generic=generic, stream=stream,
-                   kappa=getattr(p, "kappa", None))
+                   kappa=getattr(p, "kappa", None), method=method)
 
     # ------------------------------------------------------------------
     def close(self):

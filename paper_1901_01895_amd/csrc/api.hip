@@ -140,6 +140,47 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
     return prof ? prof->record(prof->lin, pl.stream) : hipSuccess;
   };
   KerrLaunch k{};
+  if (pl.method == MMNLSE_SSFM_RK4) {
+    // Eq. (4): D_half, RK4 over h on A' = N(A), D_half; the two half steps
+    // between consecutive steps are one full step exp(h L) (table E2).
+    auto one = [&](const float4 *tab) -> hipError_t {
+      if (prof && (e = prof->record(prof->lin, pl.stream)) != hipSuccess) return e;
+      if ((e = launch_linear(pl, tab, A, A, nullptr, nullptr)) != hipSuccess) return e;
+      return prof ? prof->record(prof->lin, pl.stream) : hipSuccess;
+    };
+    if (start && (e = one(E)) != hipSuccess) return e;
+    for (int64_t s = 0; s < n_steps; ++s) {
+      k = KerrLaunch{};
+      k.stage = STAGE_PLAIN;  // k1
+      k.src0 = A;
+      k.out0 = W0;
+      if ((e = kerr(k)) != hipSuccess) return e;
+      k = KerrLaunch{};
+      k.stage = STAGE_K2;  // k2 = h N(A + k1/2)
+      k.src0 = A;
+      k.src1 = W0;
+      k.out0 = W1;
+      if ((e = kerr(k)) != hipSuccess) return e;
+      k = KerrLaunch{};
+      k.stage = STAGE_K3;  // k3; W0 <- A + k3, W1 <- A + k1/6 + k2/3 + k3/3
+      k.src0 = A;
+      k.src1 = W0;
+      k.src2 = W1;
+      k.out0 = W0;
+      k.out1 = W1;
+      if ((e = kerr(k)) != hipSuccess) return e;
+      k = KerrLaunch{};
+      k.stage = STAGE_K4;  // A <- W1 + h N(W0)/6
+      k.src0 = W0;
+      k.src1 = W1;
+      k.out0 = A;
+      k.next = 0;
+      if ((e = kerr(k)) != hipSuccess) return e;
+      const bool last = s + 1 == n_steps && finish;
+      if ((e = one(last ? E : pl.E2)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   if (start) {
     k.stage = STAGE_PLAIN;
     k.src0 = A;
@@ -226,6 +267,7 @@ mmnlse_status validate_config(const mmnlse_config &c, std::string &why) {
   const double ratio = c.L_km / c.h_km;
   if (std::fabs(ratio - std::round(ratio)) > 1e-9 * std::max(1.0, ratio)) return bad("L/h is not an integer");
   if (c.precision != MMNLSE_FP32 && c.precision != MMNLSE_SPLIT_BF16) return bad("unknown precision");
+  if (c.method != MMNLSE_RK4IP && c.method != MMNLSE_SSFM_RK4) return bad("unknown method");
   for (int i = 0; i < M * c.n_beta; ++i)
     if (!std::isfinite(c.beta[i])) return bad("beta is not finite");
   if (c.alpha)
@@ -250,10 +292,11 @@ void set_last_error(const std::string &msg) { g_err = msg; }
 size_t estimate_plan_bytes(const mmnlse_config &cfg) {
   const size_t M = (size_t)cfg.M, T = (size_t)cfg.T, MT = M * T;
   size_t b = 3 * MT * sizeof(float2) + MT * sizeof(float4) + T * sizeof(float4) + 1024 * sizeof(double2);
+  if (cfg.method == MMNLSE_SSFM_RK4) b += MT * sizeof(float4);
   if (cfg.flags & MMNLSE_KERR_MANAKOV) return b + M * M * sizeof(float);
   const bool sym = (cfg.flags & MMNLSE_S_SYMMETRIC) != 0;
   const bool mfma = cfg.precision == MMNLSE_SPLIT_BF16 ||
-                    (!(cfg.flags & MMNLSE_KERR_GENERIC) && cfg.M > 8 && sym);
+                    (!(cfg.flags & MMNLSE_KERR_GENERIC) && cfg.M >= 3 && sym);
   if (mfma) {
     const size_t P = M * (M + 1) / 2, Ppad = (P + 63) / 64 * 64;
     b += Ppad * Ppad * 4 + Ppad * 4;  // FP32, or bf16 hi + lo: 4 bytes per entry either way
@@ -296,11 +339,16 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
   pl->n_steps = (int64_t)nst;
   pl->n_beta = cfg->n_beta;
   pl->precision = cfg->precision;
+  pl->method = cfg->method;
   pl->flags = cfg->flags;
   pl->stream = (hipStream_t)stream;
   hipGetDevice(&pl->device);
+  // One LDS pass per row when the row fits and there are enough rows to fill
+  // the chip; otherwise the four-step FFT, whose passes spread each row over
+  // many workgroups (2 * M single-pass workgroups would leave most CUs idle).
   const char *force4 = std::getenv("MMNLSE_FORCE_FOUR_STEP");
-  pl->four_step = T > 16384 || (force4 && force4[0] == '1' && T >= 1024);
+  pl->four_step = T > 16384 || (T >= 4096 && 2 * M < 128) || (force4 && force4[0] == '1' && T >= 1024);
+  if (force4 && force4[0] == '0' && T <= 16384) pl->four_step = false;
   if (pl->four_step) {
     pl->N1 = 1 << (pl->logT / 2);
     pl->N2 = T / pl->N1;
@@ -319,8 +367,8 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
   if (manakov) pl->kerr_path = KERR_MANAKOV;
   else if (cfg->precision == MMNLSE_SPLIT_BF16) pl->kerr_path = KERR_MFMA;
   else if (force_generic) pl->kerr_path = KERR_GENERIC;
+  else if (sym && M >= 3) pl->kerr_path = KERR_MFMA;
   else if (M <= 8) pl->kerr_path = KERR_SMALL;
-  else if (sym) pl->kerr_path = KERR_MFMA;
   else pl->kerr_path = KERR_GENERIC;
   if (fpath && !force_generic && !manakov && cfg->precision == MMNLSE_FP32) {
     const int v = std::atoi(fpath);
@@ -350,6 +398,12 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
     tabulate_E(*pl, pl->h, E);
     if ((e = dev_alloc(*pl, (void **)&pl->E, sizeof(float4) * MT)) != hipSuccess) goto nomem;
     if ((e = hipMemcpy(pl->E, E.data(), sizeof(float4) * MT, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
+  }
+  if (pl->method == MMNLSE_SSFM_RK4) {
+    std::vector<float4> E2;
+    tabulate_E(*pl, 2.0 * pl->h, E2);
+    if ((e = dev_alloc(*pl, (void **)&pl->E2, sizeof(float4) * MT)) != hipSuccess) goto nomem;
+    if ((e = hipMemcpy(pl->E2, E2.data(), sizeof(float4) * MT, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
   }
   if (pl->kerr_path == KERR_MANAKOV) {
     if ((e = dev_alloc(*pl, (void **)&pl->kappa, sizeof(float) * M * M)) != hipSuccess) goto nomem;
@@ -515,6 +569,7 @@ mmnlse_status mmnlse_step_doubling(mmnlse_t h, const void *X, double *delta) {
   g_err.clear();
   if (!h || !X || !delta) return fail(MMNLSE_E_INVALID, "null argument");
   Plan &pl = *h->pl;
+  if (pl.method != MMNLSE_RK4IP) return fail(MMNLSE_E_UNSUPPORTED, "step doubling is implemented for RK4IP plans");
   const size_t MT = (size_t)pl.M * pl.T;
   hipError_t e;
   if (!pl.E2) {

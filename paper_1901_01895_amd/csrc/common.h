@@ -79,6 +79,7 @@ struct Plan {
   int64_t n_steps = 0;
   int n_beta = 0;
   int precision = MMNLSE_FP32;
+  int method = MMNLSE_RK4IP;
   uint32_t flags = 0;
   KerrPath kerr_path = KERR_GENERIC;
   // FFT decomposition: single pass in LDS when !four_step, else T = N1 * N2
@@ -94,7 +95,8 @@ struct Plan {
   // device tables
   float4 *tw = nullptr;   // [T] exp(-2 pi i j / T) as FP32 hi + lo
   float4 *E = nullptr;    // [M][T] exp(h/2 L)/T as hi + lo, in the FFT's storage order
-  float4 *E2 = nullptr;   // same for step 2h (step doubling), built on first use
+  float4 *E2 = nullptr;   // same for step 2h, i.e. exp(h L)/T: the split-step's full
+                          // linear step and the step-doubling coarse step
   float *Sg = nullptr;    // generic tensor layout [p][n][m][l]
   float *kappa = nullptr; // Manakov coupling matrix [a][b]
   // packed symmetric tensor (matrix-core path): rows r = (p<=n), cols q = (l<=m)

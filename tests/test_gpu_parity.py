@@ -50,7 +50,9 @@ def make(mm, M, T, dt=0.5, beta=None, S=None, gamma=1.0, h=0.1, L=0.1, seed=0, *
 
 
 @pytest.mark.parametrize("T", [64, 256, 1024, 4096, 16384, 2 ** 15, 2 ** 16, 2 ** 17])
-def test_linear_half_step(gpu_lib, T):
+def test_linear_half_step(gpu_lib, T, monkeypatch):
+    """One-pass LDS FFT for every T <= 2^14 (forced), four-step above."""
+    monkeypatch.setenv("MMNLSE_FORCE_FOUR_STEP", "0")
     mm = gpu_lib
     M = 3
     print(f"linear_half_step T={T}", flush=True)
@@ -92,14 +94,17 @@ def test_linear_with_attenuation(gpu_lib):
 
 
 @pytest.mark.parametrize("M,sym,generic,path", [
-    (1, True, False, "small"), (2, False, False, "small"), (3, True, False, "small"),
+    (1, True, False, "small"), (2, False, False, "small"), (2, True, False, "small"),
     (6, True, False, "small"), (8, False, False, "small"), (5, False, True, "tiled"),
     (12, True, True, "tiled"), (13, False, False, "tiled"),
+    (3, True, False, "mfma"), (6, True, False, "mfma"),
     (9, True, False, "mfma"), (12, True, False, "mfma"), (36, True, False, "mfma"),
     (70, True, False, "mfma")])
-def test_kerr_term(gpu_lib, M, sym, generic, path):
+def test_kerr_term(gpu_lib, M, sym, generic, path, monkeypatch):
     mm = gpu_lib
     T = 512
+    if path == "small" and sym and M > 2:
+        monkeypatch.setenv("MMNLSE_KERR_PATH", "0")  # keep the register kernel covered
     print(f"kerr M={M} sym={sym} generic={generic}", flush=True)
     rng = np.random.default_rng((13, M))
     S = (W.symmetric_gaussian_tensor(M, rng) if sym else rng.standard_normal((M,) * 4)).astype(np.float32)
@@ -252,4 +257,27 @@ def test_manakov_propagation(gpu_lib):
     assert err < 1e-5
     # attenuation: power decays as exp(-alpha L) exactly (the Kerr term conserves it)
     assert abs(st["power_out"] / st["power_in"] / np.exp(-p.alpha[0] * p.L) - 1) < 1e-5
+    P.close()
+
+
+@pytest.mark.parametrize("name,kw", [("qpsk6", dict(T=2 ** 12, n_steps=20)),
+                                     ("wdm36", dict(T=2 ** 12, n_steps=10))])
+def test_ssfm_rk4_propagation(gpu_lib, name, kw):
+    """The paper's SSFM-RK4 variant (Eq. 4) through the same kernels vs the oracle."""
+    mm = gpu_lib
+    p = W.make_problem(name, **kw)
+    P = mm.Propagator.from_problem(p, method=mm.SSFM_RK4)
+    out = P.propagate(p.A0)
+    kern = oracle.KerrPacked(p.S, p.gamma)
+    ref = oracle.propagate(p.A0, p.beta, None, p.S, p.gamma, p.dt, p.h, p.n_steps, kerr=kern,
+                           method="ssfm_rk4")
+    err = rel(out, ref)
+    print(f"ssfm {name}: rel L2 = {err:.3e}", flush=True)
+    assert err < 1e-5
+    # device-resident advance equals the host-path propagation bit for bit
+    import torch
+    A = dev(p.A0)
+    P.advance(A, p.n_steps)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(A), out)
     P.close()

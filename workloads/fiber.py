@@ -283,8 +283,10 @@ def soliton_problem(T: int = 4096, window: float = 100.0, T0: float = 2.0,
 
 
 def make_problem(name: str, T: int | None = None, n_steps: int | None = None,
-                 M: int | None = None) -> Problem:
-    """Build one of the named workloads; T, n_steps and M may be reduced for tests."""
+                 M: int | None = None, tensor: tuple | None = None) -> Problem:
+    """Build one of the named workloads; T, n_steps and M may be reduced for tests.
+    ``tensor`` = (S, info) of an earlier call with the same name and M skips
+    regenerating the coupling tensor (it does not depend on T)."""
     if name == "soliton":
         kw = {}
         if T is not None:
@@ -296,21 +298,21 @@ def make_problem(name: str, T: int | None = None, n_steps: int | None = None,
         cfg, M = 1, (M or 6)
         T = T or 2 ** 14
         A, dt = shaped_field(_rng(cfg, STREAM_SYMBOLS), M, T, 8, 1, 0.05, "qpsk", _dbm(0.0))
-        S, info = coupling_tensor(M, cfg)
+        S, info = tensor if tensor is not None else coupling_tensor(M, cfg)
         return Problem(name, A.astype(np.complex64), _random_beta(M, cfg), np.zeros(M), S, 1.0,
                        dt, 0.1, n_steps or 100, True, info)
     if name == "wdm36":
         cfg, M = 2, (M or 36)
         T = T or 2 ** 16
         A, dt = shaped_field(_rng(cfg, STREAM_SYMBOLS), M, T, 32, 8, 0.05, "16qam", _dbm(-2.0))
-        S, info = coupling_tensor(M, cfg, mask_frac=0.7)
+        S, info = tensor if tensor is not None else coupling_tensor(M, cfg, mask_frac=0.7)
         return Problem(name, A.astype(np.complex64), _random_beta(M, cfg), np.zeros(M), S, 1.0,
                        dt, 0.05, n_steps or 1000, True, info)
     if name == "wdm120":
         cfg, M = 4, (M or 120)
         T = T or 2 ** 17
         A, dt = shaped_field(_rng(cfg, STREAM_SYMBOLS), M, T, 16, 4, 0.05, "qpsk", _dbm(-3.0))
-        S, info = coupling_tensor(M, cfg)
+        S, info = tensor if tensor is not None else coupling_tensor(M, cfg)
         return Problem(name, A.astype(np.complex64), table3_beta(M), np.zeros(M), S, 0.5,
                        dt, 0.02, n_steps or 500, True, info)
     raise ValueError(f"unknown workload {name!r}")
