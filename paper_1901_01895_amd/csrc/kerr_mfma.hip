@@ -46,26 +46,45 @@ struct MArgs {
 // Output row of accumulator register v for lane-half `half` of a 32x32 tile.
 __device__ __forceinline__ int acc_row(int v, int half) { return 8 * (v >> 2) + 4 * half + (v & 3); }
 
+// Orders the LDS accesses made before it by some lanes of the wave against
+// those made after it by other lanes.  A wave's LDS operations complete in
+// issue order, so this only has to stop the compiler from moving, merging or
+// sinking per-lane code across it (it emits no instruction).
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int TT>
 __device__ __forceinline__ void scatter_tile(const MArgs &a, const floatx16 &cre, const floatx16 &cim,
                                              int rt, const float2 *Xs, float2 *Os, int lane, int col) {
   const int half = lane >> 5;
+  // the 32 (p, n) pairs of this row tile, loaded together before use
+  const int4 *pt = (const int4 *)(a.pairs + rt * 32);
+  int4 pq[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) pq[i] = pt[i];
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       // one lane-half at a time: its 32 lanes share the row, so the LDS
-      // read-modify-writes below touch 32 distinct samples
+      // read-modify-writes below touch 32 distinct samples; the two halves
+      // share the samples, so their updates must not overlap
       if (half == h) {
-        const int i = rt * 32 + acc_row(v, h);
+        const int r = acc_row(v, h);
+        const int i = rt * 32 + r;
         if (i < a.P) {
-          const int ab = a.pairs[i];
+          const int4 q4 = pq[r >> 2];
+          const int ab = (r & 3) == 0 ? q4.x : (r & 3) == 1 ? q4.y : (r & 3) == 2 ? q4.z : q4.w;
           const int p = ab & 0xffff, n = ab >> 16;
           const float2 C = make_float2(cre[v], cim[v]);
           Os[p * TT + col] = cfma_conj(Os[p * TT + col], C, Xs[n * TT + col]);
           if (p != n) Os[n * TT + col] = cfma_conj(Os[n * TT + col], C, Xs[p * TT + col]);
         }
       }
+      wave_lds_order();
     }
   }
 }
@@ -90,13 +109,14 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
     float4 av[RT], an[RT];
 #pragma unroll
     for (int j = 0; j < RT; ++j) av[j] = Ab[(size_t)j * nk * 64];
+    int4 p0 = *(const int4 *)(a.pairs), p1 = *(const int4 *)(a.pairs + 4), pn0 = p0, pn1 = p1;
     for (int kq = 0; kq < nk; ++kq) {
       if (kq + 1 < nk) {
 #pragma unroll
         for (int j = 0; j < RT; ++j) an[j] = Ab[((size_t)j * nk + kq + 1) * 64];
+        pn0 = *(const int4 *)(a.pairs + 8 * (kq + 1));
+        pn1 = *(const int4 *)(a.pairs + 8 * (kq + 1) + 4);
       }
-      const int4 p0 = *(const int4 *)(a.pairs + 8 * kq);
-      const int4 p1 = *(const int4 *)(a.pairs + 8 * kq + 4);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int lo = s == 0 ? p0.x : s == 1 ? p0.z : s == 2 ? p1.x : p1.z;
@@ -115,6 +135,8 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
       }
 #pragma unroll
       for (int j = 0; j < RT; ++j) av[j] = an[j];
+      p0 = pn0;
+      p1 = pn1;
     }
   } else {
     const int nk = a.Ppad / 16;  // k-steps of 16
@@ -126,6 +148,9 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
       ah[j] = Hb[(size_t)j * nk * 64];
       al[j] = Lb[(size_t)j * nk * 64];
     }
+    // this lane half's 8 pair entries of the k-step, prefetched one step ahead
+    const int4 *pq = (const int4 *)(a.pairs + 8 * half);
+    int4 q0 = pq[0], q1 = pq[1], qn0 = q0, qn1 = q1;
     for (int ks = 0; ks < nk; ++ks) {
       if (ks + 1 < nk) {
 #pragma unroll
@@ -133,12 +158,14 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
           ahn[j] = Hb[((size_t)j * nk + ks + 1) * 64];
           aln[j] = Lb[((size_t)j * nk + ks + 1) * 64];
         }
+        qn0 = pq[4 * (ks + 1)];
+        qn1 = pq[4 * (ks + 1) + 1];
       }
-      const int *pp = a.pairs + 16 * ks + 8 * half;
       bf16x8 rh, rl, ih, il;
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int ab = pp[e];
+        const int4 qq = e < 4 ? q0 : q1;
+        const int ab = (e & 3) == 0 ? qq.x : (e & 3) == 1 ? qq.y : (e & 3) == 2 ? qq.z : qq.w;
         const float2 xa = Xs[(ab & 0xffff) * TT + col];
         const float2 xb = Xs[(ab >> 16) * TT + col];
         const float bre = fmaf(xa.x, xb.x, -xa.y * xb.y);
@@ -165,6 +192,8 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
         ah[j] = ahn[j];
         al[j] = aln[j];
       }
+      q0 = qn0;
+      q1 = qn1;
     }
   }
 #pragma unroll
@@ -403,9 +432,10 @@ hipError_t go_split_coop(const MArgs &a, KerrStage st, hipStream_t s) {
 template <bool SPLIT>
 hipError_t go_w(const MArgs &a, KerrStage st, hipStream_t s) {
   if (SPLIT) {
+    // cooperative B (measured slower on wdm36: 3.7 vs 2.4 ms/step) stays opt-in
     static const int coop_env = [] {
       const char *e = std::getenv("MMNLSE_SPLIT_COOP");
-      return e ? std::atoi(e) : 1;
+      return e ? std::atoi(e) : 0;
     }();
     if (coop_env) return go_split_coop(a, st, s);
   }
