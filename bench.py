@@ -145,7 +145,12 @@ def main():
     ap.add_argument("--rate", type=float, default=None, help="serving: Poisson rate 1/s (default saturated)")
     ap.add_argument("--steps-per-tick", type=int, default=8)
     ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU work: write the HBM-traffic record of two rocprofv3 --pmc runs")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(*args.summarize_pmc, args.workload, args.precision)))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the RK4IP path here is single-device (fields and the "
@@ -189,6 +194,57 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, precision: str) -> dict:
+    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE, ``--precision-only``) into profiles/<kernel>_<workload>_pmc.json.
+
+    The counters read KiB per dispatch.  Each is scaled by what it reads for
+    the plain device-to-device copy of the field that the timed region starts
+    with (M*T*8 bytes read and written; the copyBuffer dispatch with the
+    largest reading), and averaged over the dispatches of the dominant Kerr
+    kernel, like the per-launch duration in the roofline.
+    """
+    import csv
+    import glob
+    import hashlib
+    import re
+    import workloads as W
+
+    def load(d, counter):
+        out = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r.get("Counter_Name") == counter:
+                    key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+                    out[key] = out.get(key, 0.0) + float(r["Counter_Value"])
+        return out
+
+    p = W.make_problem(workload)
+    copy_bytes = float(p.M * p.T * 8)
+    split = "true" if precision == "split_bf16" else "false"
+    pat = re.compile(r"kerr_mfma<\d+, \d+, " + split + ",")
+    fe, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
+    rec = {"kernel": f"kerr_mfma_{precision}", "workload": workload, "source": "kerr_mfma.hip"}
+    src = os.path.join(ROOT, "paper_1901_01895_amd", "csrc", rec["source"])
+    rec["source_sha256"] = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for name, m in (("fetch", fe), ("write", wr)):
+        copy = max([v for (_, k), v in m.items() if "copyBuffer" in k] or [0.0])
+        vals = [v for (_, k), v in m.items() if pat.search(k)]
+        if not copy or not vals:
+            raise SystemExit(f"no {name} counters for the copy or the Kerr kernel under the given folder")
+        rec[f"{name}_kib_per_launch"] = sum(vals) / len(vals)
+        rec[f"{name}_launches"] = len(vals)
+        rec[f"{name}_copy_kib"] = copy
+        rec[f"{name}_factor"] = copy_bytes / (copy * 1024.0)
+    rec["copy_bytes"] = copy_bytes
+    rec["bytes_per_launch"] = 1024.0 * (rec["fetch_kib_per_launch"] * rec["fetch_factor"]
+                                        + rec["write_kib_per_launch"] * rec["write_factor"])
+    path = os.path.join(ROOT, "profiles", f"{rec['kernel']}_{workload}_pmc.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
 
 
 def traffic_for(kernel: str, workload: str):
