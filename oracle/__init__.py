@@ -20,6 +20,9 @@ from .rk4ip import (  # noqa: F401
     linear_operator,
     power,
     propagate,
+    propagate_adaptive,
+    propagate_steps,
+    StepControlError,
     rk4ip_step,
     ssfm_rk4_step,
     step_doubling_estimate,

@@ -38,7 +38,11 @@ Pins (tests/test_oracle_pins.py, all CPU):
 * Manakov/XPM form of Eq. (1): exact per-mode phase rotation without
   dispersion, and equality with the tensor form S_plmn = kappa_pm d_lp d_mn;
 * SSFM-RK4 (Eq. 4): exact for the linear part, identical to RK4IP without
-  dispersion, second order on the soliton.
+  dispersion, second order on the soliton;
+* adaptive step size (step doubling): exact and doubling steps for the
+  linear part, accepted steps scaling as tol^(-1/5) (fifth-order local
+  error, Section 3.2), global error below the summed local tolerances,
+  recovery from an oversized first step.
 
 Units: t in ps, z in km, power in W, w in rad/ps, beta_n in ps^n/km.
 """
@@ -52,7 +56,8 @@ import numpy as np
 __all__ = [
     "time_grid", "angular_frequencies", "linear_operator", "half_step_propagator",
     "apply_linear", "KerrGeneric", "KerrPacked", "KerrManakov", "kerr_term", "rk4ip_step",
-    "propagate", "power", "step_doubling_estimate", "ssfm_rk4_step",
+    "propagate", "power", "step_doubling_estimate", "ssfm_rk4_step", "propagate_adaptive",
+    "propagate_steps", "StepControlError",
 ]
 
 
@@ -284,3 +289,77 @@ def step_doubling_estimate(A: np.ndarray, beta, alpha, S, gamma: float, dt: floa
     coarse = rk4ip_step(A, E2h, 2.0 * h, N)
     delta = float(np.linalg.norm(fine - coarse) / np.linalg.norm(fine))
     return delta, fine
+
+
+# ----------------------------------------------------------------------------
+# adaptive step size from the step-doubling estimate
+# ----------------------------------------------------------------------------
+#
+# The paper integrates with fixed steps.  The controller below is the textbook
+# step-doubling scheme for Runge-Kutta methods (Press et al., Numerical
+# Recipes, "Adaptive Stepsize Control for Runge-Kutta"), with the exponent
+# fixed by the order the paper states for RK4IP (Section 3.2: local error of
+# fifth order, so delta ~ h^5):
+#
+#   trial h from z:   coarse = one step of h,  fine = two steps of h/2,
+#                     delta  = ||fine - coarse|| / ||fine||
+#   accept iff delta <= tol: the state becomes `fine` and z advances by h;
+#   next trial:       h <- min(h_max, h * clamp(0.9 (tol/delta)^(1/5), 0.5, 2))
+#                     (factor 2 when delta == 0, 0.5 when delta is not finite),
+#                     cut to the distance left.
+
+LENGTH_EPS = 1e-12  # propagation ends when less than this fraction of the length is left
+
+
+class StepControlError(RuntimeError):
+    """The controller asked for a step below h_min or ran out of trials."""
+
+
+def step_factor(delta: float, tol: float) -> float:
+    """Next-trial step factor; a non-finite delta (a trial that overflowed) is
+    a rejection with the largest cut."""
+    if not math.isfinite(delta):
+        return 0.5
+    if delta == 0.0:
+        return 2.0
+    return min(2.0, max(0.5, 0.9 * (tol / delta) ** 0.2))
+
+
+def propagate_adaptive(A0: np.ndarray, beta: np.ndarray, alpha: np.ndarray | None, S, gamma: float,
+                       dt: float, length: float, tol: float, h_init: float, h_min: float = 0.0,
+                       h_max: float = math.inf, max_trials: int = 100000, kerr=None):
+    """Propagate over `length` with step-doubling control (see above).
+
+    Returns (A, trials) with one (z, h, delta, accepted) tuple per trial.
+    Raises StepControlError when the next step would fall below h_min or
+    max_trials trials did not reach the end.
+    """
+    A = np.array(A0, dtype=np.complex128, copy=True)
+    N = _kerr_for(S, gamma, kerr)
+    z, h, trials = 0.0, min(h_init, h_max), []
+    while length - z > LENGTH_EPS * length:
+        if h < h_min:
+            raise StepControlError(f"step {h} below h_min at z = {z}")
+        if len(trials) >= max_trials:
+            raise StepControlError(f"{max_trials} trials reached z = {z}")
+        h = min(h, length - z)
+        with np.errstate(over="ignore", invalid="ignore"):
+            delta, fine = step_doubling_estimate(A, beta, alpha, S, gamma, dt, 0.5 * h, kerr=N)
+        ok = delta <= tol   # False for NaN
+        trials.append((z, h, delta, ok))
+        if ok:
+            A = fine
+            z += h
+        h = min(h_max, h * step_factor(delta, tol))
+    return A, trials
+
+
+def propagate_steps(A0: np.ndarray, beta: np.ndarray, alpha: np.ndarray | None, S, gamma: float,
+                    dt: float, hs, kerr=None) -> np.ndarray:
+    """RK4IP steps of the given sizes, in order (each with its own exp(h/2 L))."""
+    A = np.array(A0, dtype=np.complex128, copy=True)
+    w = angular_frequencies(A.shape[1], dt)
+    N = _kerr_for(S, gamma, kerr)
+    for h in hs:
+        A = rk4ip_step(A, half_step_propagator(w, beta, alpha, h), h, N)
+    return A

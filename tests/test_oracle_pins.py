@@ -369,6 +369,92 @@ def test_ssfm_is_second_order_and_less_accurate_than_rk4ip():
 
 
 # ----------------------------------------------------------------------------
+# adaptive step size from the step-doubling estimate
+# ----------------------------------------------------------------------------
+
+def _linear_only_case():
+    rng = _rng(30)
+    M, T, dt = 2, 128, 0.25
+    beta = np.column_stack([rng.uniform(-50, 50, M), rng.uniform(-2, 2, M),
+                            rng.uniform(-3, 3, M), rng.uniform(-1, 1, M)])
+    alpha = rng.uniform(0.0, 0.5, M)
+    A0 = _crandn(rng, M, T)
+    return A0, beta, alpha, dt
+
+
+def test_adaptive_linear_part_is_exact_and_steps_double():
+    """With gamma = 0 the RK4IP step is the exact linear propagator, so every
+    trial is accepted with delta at rounding level and the step doubles until
+    the end is reached (last step cut to the distance left); the result is
+    exp(L z) A0 for the whole length."""
+    A0, beta, alpha, dt = _linear_only_case()
+    S = np.zeros((2,) * 4)
+    out, trials = oracle.propagate_adaptive(A0, beta, alpha, S, 0.0, dt, 1.0, 1e-9, 0.1)
+    assert [t[3] for t in trials] == [True] * 4
+    assert np.allclose([t[1] for t in trials], [0.1, 0.2, 0.4, 0.3], rtol=1e-12)
+    assert max(t[2] for t in trials) < 1e-13
+    w = oracle.angular_frequencies(A0.shape[1], dt)
+    exact = oracle.apply_linear(A0, oracle.half_step_propagator(w, beta, alpha, 2.0))
+    assert _rel(out, exact) < 1e-13
+
+
+def _third_order_soliton():
+    p = soliton_problem(T=1024, noise=0.0)
+    z0 = math.pi / 2 * p.meta["T0"] ** 2 / abs(p.beta[0, 2])   # soliton period
+    return p, 3.0 * p.A0, z0
+
+
+def test_adaptive_step_count_follows_fifth_order_local_error():
+    """RK4IP's local error is of fifth order (Section 3.2), so at tolerance tol
+    the accepted steps scale like tol^(-1/5): 32x tighter, twice the steps.
+    A third-order soliton compresses and splits over its period, so the
+    controller must vary h along z."""
+    p, A0, z0 = _third_order_soliton()
+    counts = []
+    for tol in (1e-6, 1e-6 / 32):
+        _, tr = oracle.propagate_adaptive(A0, p.beta, None, p.S, p.gamma, p.dt, z0, tol, 0.01)
+        hs = [t[1] for t in tr if t[3]]
+        counts.append(len(hs))
+        assert max(hs) / min(hs) > 4.0
+        assert abs(sum(hs) - z0) < 1e-12 * z0
+    assert 1.8 < counts[1] / counts[0] < 2.2
+
+
+def test_adaptive_global_error_within_summed_local_tolerance():
+    """The accepted (fine) solution carries about delta/15 <= tol/15 of local
+    error per step; the global error stays below their sum.  Reference: 4000
+    fixed steps (error ~1e-9 by the fourth-order pin)."""
+    p, A0, z0 = _third_order_soliton()
+    ref = oracle.propagate(A0, p.beta, None, p.S, p.gamma, p.dt, z0 / 4000, 4000)
+    for tol in (1e-4, 1e-6):
+        out, tr = oracle.propagate_adaptive(A0, p.beta, None, p.S, p.gamma, p.dt, z0, tol, 0.01)
+        n_acc = sum(1 for t in tr if t[3])
+        err = _rel(out, ref)
+        assert 0.0 < err < n_acc * tol / 15.0
+
+
+def test_adaptive_recovers_from_oversized_first_step():
+    """A first trial over the whole length is rejected and the step shrinks
+    until trials pass; the result matches a run started from a small step."""
+    p, A0, z0 = _third_order_soliton()
+    tol = 1e-6
+    a, tr_a = oracle.propagate_adaptive(A0, p.beta, None, p.S, p.gamma, p.dt, z0, tol, z0)
+    b, _ = oracle.propagate_adaptive(A0, p.beta, None, p.S, p.gamma, p.dt, z0, tol, 1e-3)
+    assert not tr_a[0][3] and tr_a[0][1] == z0
+    first_ok = next(i for i, t in enumerate(tr_a) if t[3])
+    # each rejection cuts the step by a factor in [0.5, 0.9)
+    assert all(0.5 * tr_a[i][1] * (1 - 1e-12) <= tr_a[i + 1][1] < 0.9 * tr_a[i][1]
+               for i in range(first_ok))
+    assert _rel(a, b) < 5e-5
+
+
+def test_adaptive_step_below_minimum_raises():
+    p, A0, z0 = _third_order_soliton()
+    with pytest.raises(oracle.StepControlError):
+        oracle.propagate_adaptive(A0, p.beta, None, p.S, p.gamma, p.dt, z0, 1e-12, 0.01, h_min=1e-3)
+
+
+# ----------------------------------------------------------------------------
 # mutants: plausible mistakes planted in a copy of the oracle must fail a pin
 # ----------------------------------------------------------------------------
 
@@ -434,3 +520,37 @@ def test_mutant_beta1_sign_fails_roll_pin():
     L = 1j * (k * dt) * w       # mistake: +i beta1 w instead of -i beta1 w
     out = np.fft.ifft(np.exp(L) * np.fft.fft(A0[0]))
     assert _rel(out, np.roll(A0[0], k)) > 0.1
+
+
+def test_mutant_half_advance_fails_adaptive_linear_pin(monkeypatch):
+    """mistake: the trial's steps cover half the distance that z is advanced by."""
+    real = R.step_doubling_estimate
+
+    def half_h(A, beta, alpha, S, gamma, dt, h, kerr=None):
+        return real(A, beta, alpha, S, gamma, dt, 0.5 * h, kerr)   # two steps of h/4
+    monkeypatch.setattr(R, "step_doubling_estimate", half_h)
+    A0, beta, alpha, dt = _linear_only_case()
+    out, _ = R.propagate_adaptive(A0, beta, alpha, np.zeros((2,) * 4), 0.0, dt, 1.0, 1e-9, 0.1)
+    w = oracle.angular_frequencies(A0.shape[1], dt)
+    exact = oracle.apply_linear(A0, oracle.half_step_propagator(w, beta, alpha, 2.0))
+    assert _rel(out, exact) > 1e-3
+
+
+def test_mutant_coarse_kept_fails_adaptive_error_pin(monkeypatch):
+    """mistake: the accepted state is the single coarse step, not the two fine ones."""
+    real = R.step_doubling_estimate
+
+    def keep_coarse(A, beta, alpha, S, gamma, dt, h, kerr=None):
+        delta, fine = real(A, beta, alpha, S, gamma, dt, h, kerr)
+        w = R.angular_frequencies(np.shape(A)[1], dt)
+        N = R._kerr_for(S, gamma, kerr)
+        coarse = R.rk4ip_step(np.asarray(A, dtype=np.complex128),
+                              R.half_step_propagator(w, beta, alpha, 2.0 * h), 2.0 * h, N)
+        return delta, coarse
+    monkeypatch.setattr(R, "step_doubling_estimate", keep_coarse)
+    p, A0, z0 = _third_order_soliton()
+    ref = oracle.propagate(A0, p.beta, None, p.S, p.gamma, p.dt, z0 / 4000, 4000)
+    tol = 1e-6
+    out, tr = R.propagate_adaptive(A0, p.beta, None, p.S, p.gamma, p.dt, z0, tol, 0.01)
+    n_acc = sum(1 for t in tr if t[3])
+    assert _rel(out, ref) > n_acc * tol / 15.0
