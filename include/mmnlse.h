@@ -48,7 +48,9 @@ typedef enum {
   MMNLSE_E_DEVICE = 3,      /* HIP runtime error */
   MMNLSE_E_NONFINITE = 4,   /* NaN or Inf found in an input or result */
   MMNLSE_E_BUSY = 5,        /* request not finished yet (serving) */
-  MMNLSE_E_UNSUPPORTED = 6  /* valid request this build does not implement */
+  MMNLSE_E_UNSUPPORTED = 6, /* valid request this build does not implement */
+  MMNLSE_E_STEP = 7         /* adaptive stepping could not reach the end (step below
+                               h_min, or max_trials used up) */
 } mmnlse_status;
 
 /* Arithmetic of the Kerr contraction; FFTs and field storage are FP32 in both. */
@@ -111,10 +113,12 @@ typedef struct mmnlse_ctx *mmnlse_t;
 
 /* Create a propagation plan on the current HIP device.
  * Copies beta, alpha and S to the device, tabulates exp(h/2 L) per mode and
- * bin in FP64 (stored as FP32 hi + lo), the FFT twiddles likewise, and the
+ * bin in FP64 on the device (stored as FP32 hi + lo), the FFT twiddles
+ * likewise on the host, and the
  * Kerr tensor in the layout of the selected kernel.  Allocates three field
  * buffers of M*T complex64 as workspace.  `stream` is a hipStream_t (NULL =
- * the default stream); the handle does not own it.
+ * the default stream); the handle does not own it.  Synchronises the stream
+ * before returning.
  * Errors: E_INVALID (sizes, L/h, symmetry flag not satisfied, split precision
  * without MMNLSE_S_SYMMETRIC), E_NOMEM, E_DEVICE. */
 mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *out);
@@ -164,6 +168,55 @@ mmnlse_status mmnlse_power(mmnlse_t h, const void *X, double *out);
  * The error of the fine result is about delta/15 (fourth order, Section
  * 3.2).  X is not modified.  Synchronises. */
 mmnlse_status mmnlse_step_doubling(mmnlse_t h, const void *X, double *delta);
+
+/* Adaptive step size driven by the step-doubling estimate.  The paper uses
+ * fixed steps; the control is the textbook step-doubling scheme for
+ * Runge-Kutta methods, with the exponent 1/5 from the fifth-order local
+ * error of RK4IP (Section 3.2):
+ *   a trial of size h from position z takes one RK4IP step of h and two of
+ *   h/2 from the same state and computes delta = ||fine - coarse|| / ||fine||
+ *   (FP64 reduction; 0 for an all-zero field); it is accepted when
+ *   delta <= tol, and then the state becomes the fine result and z += h;
+ *   the next trial is h * clamp(0.9 (tol/delta)^(1/5), 0.5, 2) (2 when
+ *   delta == 0, 0.5 when delta is not finite), at most h_max, cut to the
+ *   distance left.  The propagation ends when less than 1e-12 of the length
+ *   is left.
+ * The plan's own h, L and tables are not used or changed; the propagator
+ * tables for each new trial step are built on the device. */
+typedef struct {
+  double length_km;   /* distance to propagate, > 0 */
+  double tol;         /* acceptance bound on delta, > 0 */
+  double h_init_km;   /* first trial step, > 0 */
+  double h_min_km;    /* a trial step below this fails with E_STEP (0 = no bound) */
+  double h_max_km;    /* largest trial step (0 = no bound) */
+  int64_t max_trials; /* bound on the number of trials, > 0 */
+} mmnlse_adaptive_config;
+
+typedef struct {
+  double z_km;        /* position at the start of the trial */
+  double h_km;        /* trial step */
+  double delta;       /* ||fine - coarse|| / ||fine|| */
+  int32_t accepted;   /* 1 if the fine result was kept */
+  int32_t reserved;
+} mmnlse_trial;
+
+typedef struct {
+  double z_km;        /* distance covered (the length on success) */
+  double h_next_km;   /* step the controller would try next */
+  int64_t accepted, rejected, trials;
+  double seconds;     /* host wall time of the call */
+} mmnlse_adaptive_result;
+
+/* Propagate the device-resident complex64 field A[M][T] in place over
+ * ac->length_km with adaptive steps (RK4IP plans only, else E_UNSUPPORTED).
+ * The first min(trials, log_cap) trials are written to `log` (host array,
+ * may be NULL when log_cap == 0); `res` (host) is always filled.
+ * Synchronises once per trial to read delta.  On E_STEP, A holds the state
+ * at res->z_km.  Allocates on first use two more tables and two fields of
+ * M*T (kept until destroy).  Errors: E_INVALID, E_NOMEM, E_STEP, E_DEVICE. */
+mmnlse_status mmnlse_propagate_adaptive(mmnlse_t h, void *A, const mmnlse_adaptive_config *ac,
+                                        mmnlse_trial *log, int64_t log_cap,
+                                        mmnlse_adaptive_result *res);
 
 /* Measurement: run n_steps exactly like mmnlse_advance, with a HIP event
  * pair recorded on the handle's stream around every kernel-class launch,

@@ -287,7 +287,8 @@ def step_doubling_estimate(A: np.ndarray, beta, alpha, S, gamma: float, dt: floa
     E2h = half_step_propagator(w, beta, alpha, 2.0 * h)
     fine = rk4ip_step(rk4ip_step(A, Eh, h, N), Eh, h, N)
     coarse = rk4ip_step(A, E2h, 2.0 * h, N)
-    delta = float(np.linalg.norm(fine - coarse) / np.linalg.norm(fine))
+    nf, nd = np.linalg.norm(fine), np.linalg.norm(fine - coarse)
+    delta = float(nd / nf) if nf > 0 else (0.0 if nd == 0 else math.nan)   # 0 for a zero field
     return delta, fine
 
 

@@ -23,12 +23,13 @@ S_SYMMETRIC, KERR_GENERIC, KERR_MANAKOV = 0x1, 0x2, 0x4
 KERR_PATHS = {0: "small", 1: "tiled", 2: "mfma", 3: "manakov"}
 
 STATUS = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NONFINITE", 5: "E_BUSY",
-          6: "E_UNSUPPORTED"}
+          6: "E_UNSUPPORTED", 7: "E_STEP"}
 
 SYMBOLS = (
     "mmnlse_create", "mmnlse_destroy", "mmnlse_last_error", "mmnlse_propagate", "mmnlse_advance",
     "mmnlse_linear_half_step", "mmnlse_kerr", "mmnlse_power", "mmnlse_step_doubling",
     "mmnlse_synchronize", "mmnlse_footprint", "mmnlse_kerr_path", "mmnlse_profile",
+    "mmnlse_propagate_adaptive",
     "mmnlse_server_create", "mmnlse_server_submit", "mmnlse_server_poll", "mmnlse_server_wait",
     "mmnlse_server_stats", "mmnlse_server_destroy",
 )
@@ -68,6 +69,22 @@ class Stats(ctypes.Structure):
                 ("seconds", ctypes.c_double), ("steps", ctypes.c_int64)]
 
 
+class AdaptiveConfig(ctypes.Structure):
+    _fields_ = [("length_km", ctypes.c_double), ("tol", ctypes.c_double), ("h_init_km", ctypes.c_double),
+                ("h_min_km", ctypes.c_double), ("h_max_km", ctypes.c_double),
+                ("max_trials", ctypes.c_int64)]
+
+
+class Trial(ctypes.Structure):
+    _fields_ = [("z_km", ctypes.c_double), ("h_km", ctypes.c_double), ("delta", ctypes.c_double),
+                ("accepted", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class AdaptiveResult(ctypes.Structure):
+    _fields_ = [("z_km", ctypes.c_double), ("h_next_km", ctypes.c_double), ("accepted", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("trials", ctypes.c_int64), ("seconds", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -94,6 +111,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mmnlse_footprint.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.mmnlse_kerr_path.argtypes = [vp, ctypes.POINTER(i32)]
     lib.mmnlse_profile.argtypes = [vp, vp, i64, dp, ctypes.POINTER(ctypes.c_int64)]
+    lib.mmnlse_propagate_adaptive.argtypes = [vp, vp, ctypes.POINTER(AdaptiveConfig), ctypes.POINTER(Trial),
+                                              i64, ctypes.POINTER(AdaptiveResult)]
     lib.mmnlse_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     lib.mmnlse_server_submit.argtypes = [vp, ctypes.POINTER(Config), vp, i32, ctypes.POINTER(ctypes.c_uint64)]
     for fn in (lib.mmnlse_server_poll, lib.mmnlse_server_wait):
@@ -258,6 +277,28 @@ class Propagator:
         out = ctypes.c_double()
         _check(load().mmnlse_step_doubling(self._h, ctypes.c_void_p(_dptr(X)), ctypes.byref(out)))
         return out.value
+
+    def propagate_adaptive(self, A, length: float, tol: float, h_init: float, h_min: float = 0.0,
+                           h_max: float = 0.0, max_trials: int = 100000, log_cap: int = 100000):
+        """Adaptive-step propagation of device field A in place (mmnlse_propagate_adaptive).
+
+        Returns (result dict, trials) with trials a list of (z, h, delta, accepted)
+        tuples.  On E_STEP raises MMNLSEError whose ``result`` and ``trials``
+        attributes hold the same for the part that was covered.
+        """
+        ac = AdaptiveConfig(float(length), float(tol), float(h_init), float(h_min), float(h_max),
+                            int(max_trials))
+        log = (Trial * max(int(log_cap), 1))()
+        res = AdaptiveResult()
+        st = load().mmnlse_propagate_adaptive(self._h, ctypes.c_void_p(_dptr(A)), ctypes.byref(ac), log,
+                                              int(log_cap), ctypes.byref(res))
+        out = {k: getattr(res, k) for k, _ in AdaptiveResult._fields_}
+        trials = [(t.z_km, t.h_km, t.delta, bool(t.accepted)) for t in log[:min(res.trials, int(log_cap))]]
+        if st != 0:
+            err = MMNLSEError(st, load().mmnlse_last_error().decode())
+            err.result, err.trials = out, trials
+            raise err
+        return out, trials
 
     def profile(self, A, n_steps: int) -> dict:
         """Advance A in place by n_steps with HIP events around every launch;

@@ -47,44 +47,6 @@ static inline float4 split_hilo(double re, double im) {
 // Tabulate E_p(f) = exp(h/2 * L_p(w_f)) / T in the FFT's storage order;
 // L_p(w) = -alpha_p/2 + i sum_n beta_{n,p} (-w)^n / n! (Eq. 1 in the
 // frequency domain with the exp(-i w t) forward kernel), w_f = 2 pi fftfreq.
-static void tabulate_E(const Plan &pl, double h, std::vector<float4> &E) {
-  const int M = pl.M, T = pl.T;
-  E.resize((size_t)M * T);
-  auto work = [&](int p0, int p1) {
-    std::vector<double> fact(pl.n_beta + 1, 1.0);
-    for (int n = 1; n <= pl.n_beta; ++n) fact[n] = fact[n - 1] * n;
-    for (int p = p0; p < p1; ++p) {
-      const double *b = pl.beta_h + (size_t)p * pl.n_beta;
-      const double a = pl.alpha_h ? pl.alpha_h[p] : 0.0;
-      for (int pos = 0; pos < T; ++pos) {
-        int f = pos;
-        if (pl.four_step) {  // position N2*k1 + k2 holds bin k1 + N1*k2
-          const int k1 = pos / pl.N2, k2 = pos % pl.N2;
-          f = k1 + pl.N1 * k2;
-        }
-        const double freq = (f < (T + 1) / 2 ? (double)f : (double)(f - T)) / ((double)T * pl.dt);
-        const double w = 2.0 * M_PI * freq;
-        double phase = 0.0, pw = 1.0;
-        for (int n = 0; n < pl.n_beta; ++n) {
-          phase += b[n] * pw / fact[n];
-          pw *= -w;
-        }
-        const double mag = std::exp(-0.25 * h * a) / (double)T;
-        const double ang = 0.5 * h * phase;
-        E[(size_t)p * T + pos] = split_hilo(mag * std::cos(ang), mag * std::sin(ang));
-      }
-    }
-  };
-  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  if (M < 2 || (size_t)M * T < (1u << 16)) nth = 1;
-  std::vector<std::thread> th;
-  for (unsigned i = 0; i < nth; ++i) {
-    const int p0 = (int)((int64_t)M * i / nth), p1 = (int)((int64_t)M * (i + 1) / nth);
-    if (p1 > p0) th.emplace_back(work, p0, p1);
-  }
-  for (auto &t : th) t.join();
-}
-
 static hipError_t dev_alloc(Plan &pl, void **p, size_t bytes) {
   hipError_t e = hipMalloc(p, bytes);
   if (e == hipSuccess) pl.bytes += bytes;
@@ -96,17 +58,20 @@ static void free_plan(Plan *pl) {
   hipFree(pl->tw);
   hipFree(pl->E);
   hipFree(pl->E2);
+  hipFree(pl->Ea);
+  hipFree(pl->Eb);
+  hipFree(pl->beta_d);
+  hipFree(pl->alpha_d);
   hipFree(pl->Sg);
   hipFree(pl->kappa);
   hipFree(pl->Sp);
   hipFree(pl->Sph);
   hipFree(pl->Spl);
   hipFree(pl->pairs);
+  hipFree(pl->koff);
   for (auto &b : pl->buf) hipFree(b);
   for (auto &b : pl->sd) hipFree(b);
   hipFree(pl->red);
-  delete[] pl->beta_h;
-  delete[] pl->alpha_h;
   delete pl;
 }
 
@@ -293,6 +258,7 @@ size_t estimate_plan_bytes(const mmnlse_config &cfg) {
   const size_t M = (size_t)cfg.M, T = (size_t)cfg.T, MT = M * T;
   size_t b = 3 * MT * sizeof(float2) + MT * sizeof(float4) + T * sizeof(float4) + 1024 * sizeof(double2);
   if (cfg.method == MMNLSE_SSFM_RK4) b += MT * sizeof(float4);
+  b += M * (size_t)std::max(0, cfg.n_beta) * sizeof(double) + (cfg.alpha ? M * sizeof(double) : 0);
   if (cfg.flags & MMNLSE_KERR_MANAKOV) return b + M * M * sizeof(float);
   const bool sym = (cfg.flags & MMNLSE_S_SYMMETRIC) != 0;
   const bool mfma = cfg.precision == MMNLSE_SPLIT_BF16 ||
@@ -353,12 +319,6 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
     pl->N1 = 1 << (pl->logT / 2);
     pl->N2 = T / pl->N1;
   }
-  pl->beta_h = new double[(size_t)M * std::max(1, cfg->n_beta)];
-  if (cfg->n_beta) std::memcpy(pl->beta_h, cfg->beta, sizeof(double) * M * cfg->n_beta);
-  if (cfg->alpha) {
-    pl->alpha_h = new double[M];
-    std::memcpy(pl->alpha_h, cfg->alpha, sizeof(double) * M);
-  }
 
   // Kerr path
   const bool force_generic = (cfg->flags & MMNLSE_KERR_GENERIC) != 0;
@@ -393,17 +353,22 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
     if ((e = dev_alloc(*pl, (void **)&pl->tw, sizeof(float4) * T)) != hipSuccess) goto nomem;
     if ((e = hipMemcpy(pl->tw, tw.data(), sizeof(float4) * T, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
   }
-  {
-    std::vector<float4> E;
-    tabulate_E(*pl, pl->h, E);
-    if ((e = dev_alloc(*pl, (void **)&pl->E, sizeof(float4) * MT)) != hipSuccess) goto nomem;
-    if ((e = hipMemcpy(pl->E, E.data(), sizeof(float4) * MT, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
+  // coefficients, then the propagator tables built from them on the device
+  if (cfg->n_beta) {
+    const size_t nb = sizeof(double) * M * cfg->n_beta;
+    if ((e = dev_alloc(*pl, (void **)&pl->beta_d, nb)) != hipSuccess) goto nomem;
+    if ((e = hipMemcpy(pl->beta_d, cfg->beta, nb, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
   }
+  if (cfg->alpha) {
+    if ((e = dev_alloc(*pl, (void **)&pl->alpha_d, sizeof(double) * M)) != hipSuccess) goto nomem;
+    if ((e = hipMemcpy(pl->alpha_d, cfg->alpha, sizeof(double) * M, hipMemcpyHostToDevice)) != hipSuccess)
+      goto dev;
+  }
+  if ((e = dev_alloc(*pl, (void **)&pl->E, sizeof(float4) * MT)) != hipSuccess) goto nomem;
+  if ((e = launch_tabulate_E(*pl, pl->h, pl->E)) != hipSuccess) goto dev;
   if (pl->method == MMNLSE_SSFM_RK4) {
-    std::vector<float4> E2;
-    tabulate_E(*pl, 2.0 * pl->h, E2);
     if ((e = dev_alloc(*pl, (void **)&pl->E2, sizeof(float4) * MT)) != hipSuccess) goto nomem;
-    if ((e = hipMemcpy(pl->E2, E2.data(), sizeof(float4) * MT, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
+    if ((e = launch_tabulate_E(*pl, 2.0 * pl->h, pl->E2)) != hipSuccess) goto dev;
   }
   if (pl->kerr_path == KERR_MANAKOV) {
     if ((e = dev_alloc(*pl, (void **)&pl->kappa, sizeof(float) * M * M)) != hipSuccess) goto nomem;
@@ -431,6 +396,7 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
     if ((e = dev_alloc(*pl, (void **)&b, sizeof(float2) * MT)) != hipSuccess) goto nomem;
   pl->red_n = (int)std::min<size_t>(1024, std::max<size_t>(1, MT / 4096));
   if ((e = dev_alloc(*pl, (void **)&pl->red, sizeof(double2) * 1024)) != hipSuccess) goto nomem;
+  if ((e = hipStreamSynchronize(pl->stream)) != hipSuccess) goto dev;  // tables ready, errors surfaced
   {
     mmnlse_ctx *c = new (std::nothrow) mmnlse_ctx{pl};
     if (!c) {
@@ -573,13 +539,11 @@ mmnlse_status mmnlse_step_doubling(mmnlse_t h, const void *X, double *delta) {
   const size_t MT = (size_t)pl.M * pl.T;
   hipError_t e;
   if (!pl.E2) {
-    std::vector<float4> E2;
-    tabulate_E(pl, 2.0 * pl.h, E2);
     if ((e = dev_alloc(pl, (void **)&pl.E2, sizeof(float4) * MT)) != hipSuccess) {
       (void)hipGetLastError();
       return fail(MMNLSE_E_NOMEM, "device allocation failed");
     }
-    HIPCHK(hipMemcpy(pl.E2, E2.data(), sizeof(float4) * MT, hipMemcpyHostToDevice), "upload");
+    HIPCHK(launch_tabulate_E(pl, 2.0 * pl.h, pl.E2), "tabulate");
   }
   for (auto &b : pl.sd)
     if (!b && (e = dev_alloc(pl, (void **)&b, sizeof(float2) * MT)) != hipSuccess) {
@@ -596,6 +560,94 @@ mmnlse_status mmnlse_step_doubling(mmnlse_t h, const void *X, double *delta) {
   HIPCHK(reduce_norms(pl, fine, coarse, MT, &sf, &sd), "norms");
   *delta = sf > 0 ? std::sqrt(sd / sf) : 0.0;
   return MMNLSE_OK;
+}
+
+// Step-doubling control (the paper steps with a fixed h; the exponent 1/5 is
+// the fifth-order local error of RK4IP, Section 3.2): a trial of size h from z
+// runs one step of h (tables for h) and two of h/2 (tables for h/2) from the
+// same state, delta = ||fine - coarse|| / ||fine|| in FP64; the fine result is
+// kept when delta <= tol.  The next trial is h * clamp(0.9 (tol/delta)^(1/5),
+// 0.5, 2) (2 for delta == 0, 0.5 for a non-finite delta), at most h_max, cut
+// to the distance left.
+static double adaptive_factor(double delta, double tol) {
+  if (!std::isfinite(delta)) return 0.5;
+  if (delta == 0.0) return 2.0;
+  return std::min(2.0, std::max(0.5, 0.9 * std::pow(tol / delta, 0.2)));
+}
+
+mmnlse_status mmnlse_propagate_adaptive(mmnlse_t h, void *A, const mmnlse_adaptive_config *ac,
+                                        mmnlse_trial *log, int64_t log_cap, mmnlse_adaptive_result *res) {
+  g_err.clear();
+  if (!h || !A || !ac || !res) return fail(MMNLSE_E_INVALID, "null argument");
+  if (log_cap < 0 || (log_cap > 0 && !log)) return fail(MMNLSE_E_INVALID, "log_cap > 0 needs a log array");
+  Plan &pl = *h->pl;
+  if (pl.method != MMNLSE_RK4IP) return fail(MMNLSE_E_UNSUPPORTED, "adaptive stepping is implemented for RK4IP plans");
+  const double L = ac->length_km, tol = ac->tol, hmin = ac->h_min_km;
+  const double hmax = ac->h_max_km > 0 ? ac->h_max_km : HUGE_VAL;
+  if (!(L > 0) || !std::isfinite(L)) return fail(MMNLSE_E_INVALID, "length_km must be finite and > 0");
+  if (!(tol > 0) || !std::isfinite(tol)) return fail(MMNLSE_E_INVALID, "tol must be finite and > 0");
+  if (!(ac->h_init_km > 0) || !std::isfinite(ac->h_init_km)) return fail(MMNLSE_E_INVALID, "h_init_km must be > 0");
+  if (!(hmin >= 0) || !(ac->h_max_km >= 0)) return fail(MMNLSE_E_INVALID, "h_min_km and h_max_km must be >= 0");
+  if (ac->max_trials <= 0) return fail(MMNLSE_E_INVALID, "max_trials must be > 0");
+  const size_t MT = (size_t)pl.M * pl.T;
+  hipError_t e;
+  auto alloc = [&](void **p, size_t bytes) -> bool {
+    if (*p) return true;
+    if (dev_alloc(pl, p, bytes) == hipSuccess) return true;
+    (void)hipGetLastError();
+    return false;
+  };
+  if (!alloc((void **)&pl.Ea, sizeof(float4) * MT) || !alloc((void **)&pl.Eb, sizeof(float4) * MT) ||
+      !alloc((void **)&pl.sd[0], sizeof(float2) * MT) || !alloc((void **)&pl.sd[1], sizeof(float2) * MT))
+    return fail(MMNLSE_E_NOMEM, "device allocation failed");
+  float2 *X = (float2 *)A, *fine = pl.sd[0], *coarse = pl.sd[1];
+  float2 *work[2] = {pl.buf[0], pl.buf[1]};
+  *res = mmnlse_adaptive_result{};
+  const auto t0 = std::chrono::steady_clock::now();
+  double z = 0.0, step = std::min(ac->h_init_km, hmax);
+  int64_t trials = 0;
+  mmnlse_status st = MMNLSE_OK;
+  while (L - z > 1e-12 * L) {
+    if (!(step > 0) || step < hmin) {
+      st = fail(MMNLSE_E_STEP, "step size fell below h_min");
+      break;
+    }
+    if (trials >= ac->max_trials) {
+      st = fail(MMNLSE_E_STEP, "max_trials reached before the end of the fiber");
+      break;
+    }
+    step = std::min(step, L - z);
+    if (pl.Ea_h != step) {
+      pl.Ea_h = 0;
+      HIPCHK(launch_tabulate_E(pl, step, pl.Ea), "tabulate");
+      HIPCHK(launch_tabulate_E(pl, 0.5 * step, pl.Eb), "tabulate");
+      pl.Ea_h = step;
+    }
+    HIPCHK(hipMemcpyAsync(fine, X, sizeof(float2) * MT, hipMemcpyDeviceToDevice, pl.stream), "copy");
+    HIPCHK(hipMemcpyAsync(coarse, X, sizeof(float2) * MT, hipMemcpyDeviceToDevice, pl.stream), "copy");
+    HIPCHK(run_steps(pl, fine, 2, 0.5 * step, pl.Eb, work), "fine steps");
+    HIPCHK(run_steps(pl, coarse, 1, step, pl.Ea, work), "coarse step");
+    double sf = 0, sd = 0;
+    HIPCHK(reduce_norms(pl, fine, coarse, MT, &sf, &sd), "norms");
+    const double delta = sf > 0 ? std::sqrt(sd / sf) : (sd == 0 ? 0.0 : NAN);
+    const bool ok = delta <= tol;
+    if (trials < log_cap) log[trials] = mmnlse_trial{z, step, delta, ok ? 1 : 0, 0};
+    ++trials;
+    if (ok) {
+      HIPCHK(hipMemcpyAsync(X, fine, sizeof(float2) * MT, hipMemcpyDeviceToDevice, pl.stream), "copy");
+      z += step;
+      ++res->accepted;
+    } else {
+      ++res->rejected;
+    }
+    step = std::min(hmax, step * adaptive_factor(delta, tol));
+  }
+  HIPCHK(hipStreamSynchronize(pl.stream), "synchronize");
+  res->z_km = z;
+  res->h_next_km = step;
+  res->trials = trials;
+  res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return st;
 }
 
 mmnlse_status mmnlse_profile(mmnlse_t h, void *A, int64_t n_steps, double *ms, int64_t *counts) {

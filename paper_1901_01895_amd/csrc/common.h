@@ -88,15 +88,20 @@ struct Plan {
   hipStream_t stream = nullptr;
   int device = 0;
 
-  // host copies of the coefficients (for re-tabulation at other step sizes)
+  // coefficients: host copies and the device copies the tables are built from
   double *beta_h = nullptr;   // [M][n_beta]
   double *alpha_h = nullptr;  // [M]
+  double *beta_d = nullptr;   // [M][n_beta] (null when n_beta == 0)
+  double *alpha_d = nullptr;  // [M] or null for no attenuation
 
   // device tables
   float4 *tw = nullptr;   // [T] exp(-2 pi i j / T) as FP32 hi + lo
   float4 *E = nullptr;    // [M][T] exp(h/2 L)/T as hi + lo, in the FFT's storage order
   float4 *E2 = nullptr;   // same for step 2h, i.e. exp(h L)/T: the split-step's full
                           // linear step and the step-doubling coarse step
+  // adaptive stepping (lazy): exp(h/2 L)/T for the trial step h and for h/2
+  float4 *Ea = nullptr, *Eb = nullptr;
+  double Ea_h = 0;        // trial step the two tables hold (0 = none)
   float *Sg = nullptr;    // generic tensor layout [p][n][m][l]
   float *kappa = nullptr; // Manakov coupling matrix [a][b]
   // packed symmetric tensor (matrix-core path): rows r = (p<=n), cols q = (l<=m)
@@ -105,6 +110,8 @@ struct Plan {
   uint16_t *Sph = nullptr;      // bf16 hi of Sp
   uint16_t *Spl = nullptr;      // bf16 lo of Sp - hi
   int32_t *pairs = nullptr;     // [Ppad] packed (a | b << 16) for r / q index -> (a,b)
+  int32_t *koff = nullptr;      // [Ppad][2] LDS byte offsets of (X_a, X_b) per q, kernel lane order
+  int koff_tt = 0;              // tile width (samples) the offsets were built for
 
   // workspace
   float2 *buf[3] = {nullptr, nullptr, nullptr};
@@ -118,6 +125,8 @@ struct Plan {
 hipError_t launch_linear(const Plan &pl, const float4 *E, const float2 *in0, float2 *out0,
                          const float2 *in1, float2 *out1);
 hipError_t launch_kerr(const Plan &pl, double h, const KerrLaunch &k);
+// E[p][pos] = exp(h/2 L_p)/T (hi + lo) in the FFT's storage order, from beta_d / alpha_d
+hipError_t launch_tabulate_E(const Plan &pl, double h, float4 *E);
 hipError_t launch_convert_c128_to_c64(const Plan &pl, const double2 *in, float2 *out, size_t n);
 hipError_t launch_convert_c64_to_c128(const Plan &pl, const float2 *in, double2 *out, size_t n);
 // FP64 sum of |x|^2 (and of |x - y|^2 when y != nullptr) -> host values (synchronises)

@@ -39,9 +39,35 @@ struct MArgs {
   const float4 *A32;     // FP32 swizzle: [Ppad/32][Ppad/8][64] float4
   const uint4 *Ah, *Al;  // bf16 swizzle: [Ppad/32][Ppad/16][64] 8 x bf16
   const int *pairs;      // [Ppad] a | b << 16 (padding rows/cols -> (0,0), zero weight)
+  const int4 *koff;      // B operand: byte offsets of X_a, X_b rows in the LDS tile, lane order
   float hg;
-  int M, T, P, Ppad, next;
+  int M, T, P, Ppad, next, koff_tt;
 };
+
+typedef float floatv2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two floats to bf16 hi (round to nearest even) and bf16 lo = bf16(x - hi),
+// each pair packed in one register in element order.
+__device__ __forceinline__ void split2(float x0, float x1, uint32_t &hi, uint32_t &lo) {
+  const uint32_t hb = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatv2){x0, x1}, bf16x2));
+  const float r0 = x0 - __builtin_bit_cast(float, hb << 16);
+  const float r1 = x1 - __builtin_bit_cast(float, hb & 0xffff0000u);
+  hi = hb;
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatv2){r0, r1}, bf16x2));
+}
+
+// B_q = X_a X_b at the lane's sample, X_a and X_b read at byte offsets oa, ob of
+// the lane's column base xb in the LDS field tile.
+__device__ __forceinline__ float2 form_b(const char *xb, int oa, int ob) {
+  const float2 xa = *(const float2 *)(xb + oa);
+  const float2 xc = *(const float2 *)(xb + ob);
+  return make_float2(fmaf(xa.x, xc.x, -xa.y * xc.y), fmaf(xa.x, xc.y, xa.y * xc.x));
+}
+
+// Samples per workgroup (32 W) of the shape go_shape picks for M modes and T
+// samples; the contraction's offset table is built for it.
+int mfma_tile_width(int M, int T) { return M <= 64 && T % 128 == 0 ? 128 : 32; }
 
 // Output row of accumulator register v for lane-half `half` of a 32x32 tile.
 __device__ __forceinline__ int acc_row(int v, int half) { return 8 * (v >> 2) + 4 * half + (v & 3); }
@@ -97,6 +123,7 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
                                               int rt0) {
   constexpr int TT = 32 * W;
   const int half = lane >> 5;
+  const char *xb = (const char *)(Xs + col);
   floatx16 cre[RT], cim[RT];
 #pragma unroll
   for (int j = 0; j < RT; ++j) {
@@ -109,34 +136,32 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
     float4 av[RT], an[RT];
 #pragma unroll
     for (int j = 0; j < RT; ++j) av[j] = Ab[(size_t)j * nk * 64];
-    int4 p0 = *(const int4 *)(a.pairs), p1 = *(const int4 *)(a.pairs + 4), pn0 = p0, pn1 = p1;
+    // this lane half's (oa, ob) for the 4 k-steps of an iteration, one iteration ahead
+    const int4 *ko = a.koff + 2 * half;
+    int4 o0 = ko[0], o1 = ko[1], on0 = o0, on1 = o1;
     for (int kq = 0; kq < nk; ++kq) {
       if (kq + 1 < nk) {
 #pragma unroll
         for (int j = 0; j < RT; ++j) an[j] = Ab[((size_t)j * nk + kq + 1) * 64];
-        pn0 = *(const int4 *)(a.pairs + 8 * (kq + 1));
-        pn1 = *(const int4 *)(a.pairs + 8 * (kq + 1) + 4);
+        on0 = ko[4 * (kq + 1)];
+        on1 = ko[4 * (kq + 1) + 1];
       }
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
-        const int lo = s == 0 ? p0.x : s == 1 ? p0.z : s == 2 ? p1.x : p1.z;
-        const int hi = s == 0 ? p0.y : s == 1 ? p0.w : s == 2 ? p1.y : p1.w;
-        const int ab = half ? hi : lo;
-        const float2 xa = Xs[(ab & 0xffff) * TT + col];
-        const float2 xb = Xs[(ab >> 16) * TT + col];
-        const float bre = fmaf(xa.x, xb.x, -xa.y * xb.y);
-        const float bim = fmaf(xa.x, xb.y, xa.y * xb.x);
+        const int oa = s == 0 ? o0.x : s == 1 ? o0.z : s == 2 ? o1.x : o1.z;
+        const int ob = s == 0 ? o0.y : s == 1 ? o0.w : s == 2 ? o1.y : o1.w;
+        const float2 b = form_b(xb, oa, ob);
 #pragma unroll
         for (int j = 0; j < RT; ++j) {
           const float av_s = s == 0 ? av[j].x : s == 1 ? av[j].y : s == 2 ? av[j].z : av[j].w;
-          cre[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, bre, cre[j], 0, 0, 0);
-          cim[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, bim, cim[j], 0, 0, 0);
+          cre[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, b.x, cre[j], 0, 0, 0);
+          cim[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, b.y, cim[j], 0, 0, 0);
         }
       }
 #pragma unroll
       for (int j = 0; j < RT; ++j) av[j] = an[j];
-      p0 = pn0;
-      p1 = pn1;
+      o0 = on0;
+      o1 = on1;
     }
   } else {
     const int nk = a.Ppad / 16;  // k-steps of 16
@@ -148,9 +173,11 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
       ah[j] = Hb[(size_t)j * nk * 64];
       al[j] = Lb[(size_t)j * nk * 64];
     }
-    // this lane half's 8 pair entries of the k-step, prefetched one step ahead
-    const int4 *pq = (const int4 *)(a.pairs + 8 * half);
-    int4 q0 = pq[0], q1 = pq[1], qn0 = q0, qn1 = q1;
+    // this lane half's (oa, ob) for the 8 pairs of a k-step, one step ahead
+    const int4 *ko = a.koff + 4 * half;
+    int4 o[4], on[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) on[i] = o[i] = ko[i];
     for (int ks = 0; ks < nk; ++ks) {
       if (ks + 1 < nk) {
 #pragma unroll
@@ -158,24 +185,21 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
           ahn[j] = Hb[((size_t)j * nk + ks + 1) * 64];
           aln[j] = Lb[((size_t)j * nk + ks + 1) * 64];
         }
-        qn0 = pq[4 * (ks + 1)];
-        qn1 = pq[4 * (ks + 1) + 1];
-      }
-      bf16x8 rh, rl, ih, il;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int4 qq = e < 4 ? q0 : q1;
-        const int ab = (e & 3) == 0 ? qq.x : (e & 3) == 1 ? qq.y : (e & 3) == 2 ? qq.z : qq.w;
-        const float2 xa = Xs[(ab & 0xffff) * TT + col];
-        const float2 xb = Xs[(ab >> 16) * TT + col];
-        const float bre = fmaf(xa.x, xb.x, -xa.y * xb.y);
-        const float bim = fmaf(xa.x, xb.y, xa.y * xb.x);
-        const __bf16 hr = (__bf16)bre, hi = (__bf16)bim;
-        rh[e] = hr;
-        ih[e] = hi;
-        rl[e] = (__bf16)(bre - (float)hr);
-        il[e] = (__bf16)(bim - (float)hi);
+        for (int i = 0; i < 4; ++i) on[i] = ko[8 * (ks + 1) + i];
       }
+      uint32_t urh[4], url[4], uih[4], uil[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {  // elements 2i and 2i+1
+        const float2 b0 = form_b(xb, o[i].x, o[i].y);
+        const float2 b1 = form_b(xb, o[i].z, o[i].w);
+        split2(b0.x, b1.x, urh[i], url[i]);
+        split2(b0.y, b1.y, uih[i], uil[i]);
+      }
+      const bf16x8 rh = __builtin_bit_cast(bf16x8, make_uint4(urh[0], urh[1], urh[2], urh[3]));
+      const bf16x8 rl = __builtin_bit_cast(bf16x8, make_uint4(url[0], url[1], url[2], url[3]));
+      const bf16x8 ih = __builtin_bit_cast(bf16x8, make_uint4(uih[0], uih[1], uih[2], uih[3]));
+      const bf16x8 il = __builtin_bit_cast(bf16x8, make_uint4(uil[0], uil[1], uil[2], uil[3]));
 #pragma unroll
       for (int j = 0; j < RT; ++j) {
         const bf16x8 sh = __builtin_bit_cast(bf16x8, ah[j]);
@@ -192,8 +216,8 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
         ah[j] = ahn[j];
         al[j] = aln[j];
       }
-      q0 = qn0;
-      q1 = qn1;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) o[i] = on[i];
     }
   }
 #pragma unroll
@@ -387,6 +411,7 @@ __global__ __launch_bounds__(64 * W * R) void kerr_mfma(MArgs a) {
 template <int W, int R, bool SPLIT, int RTM, bool COOP = false>
 hipError_t go(const MArgs &a, KerrStage st, hipStream_t s) {
   constexpr int TT = 32 * W;
+  if (!COOP && a.koff_tt != TT) return hipErrorInvalidValue;  // offsets built for another tile width
   const dim3 grid(a.T / TT), block(64 * W * R);
   const size_t shm = (size_t)(1 + R) * a.M * TT * sizeof(float2) + (COOP ? 2 * W * 4 * 32 * 16 * 2 : 0);
   auto launch = [&](auto kern) -> hipError_t {
@@ -413,7 +438,7 @@ hipError_t go(const MArgs &a, KerrStage st, hipStream_t s) {
 //   M <= 208: 1 x 2;   M <= 256: 1 x 1
 template <bool SPLIT, int RTM>
 hipError_t go_shape(const MArgs &a, KerrStage st, hipStream_t s) {
-  if (a.M <= 64 && a.T % 128 == 0) return go<4, 1, SPLIT, RTM>(a, st, s);
+  if (mfma_tile_width(a.M, a.T) == 128) return go<4, 1, SPLIT, RTM>(a, st, s);
   if (a.M <= 125) return go<1, 4, SPLIT, RTM>(a, st, s);
   if (a.M <= 208) return go<1, 2, SPLIT, RTM>(a, st, s);
   return go<1, 1, SPLIT, RTM>(a, st, s);
@@ -478,6 +503,8 @@ hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k) {
   a.Ah = (const uint4 *)pl.Sph;
   a.Al = (const uint4 *)pl.Spl;
   a.pairs = pl.pairs;
+  a.koff = (const int4 *)pl.koff;
+  a.koff_tt = pl.koff_tt;
   a.hg = (float)(h * pl.gamma);
   a.M = pl.M;
   a.T = pl.T;
@@ -523,6 +550,23 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
     return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
   };
   if ((e = alloc_copy((void **)&pl.pairs, pairs.data(), sizeof(int32_t) * Ppad)) != hipSuccess) return e;
+  // B-operand offsets (bytes into the LDS field tile [M][TT] float2) of X_a and
+  // X_b for column q, in the order a lane reads them: split path q = 16 ks +
+  // 8 half + e (natural order); FP32 path q = 8 kq + 2 s + half stored at
+  // ((kq * 2 + half) * 4 + s).
+  const int TT = mfma_tile_width(M, pl.T);
+  std::vector<int32_t> koff(2 * (size_t)Ppad);
+  for (int q = 0; q < Ppad; ++q) {
+    size_t slot = q;
+    if (pl.precision != MMNLSE_SPLIT_BF16) {
+      const int kq = q / 8, s = (q % 8) / 2, hf = q % 2;
+      slot = ((size_t)kq * 2 + hf) * 4 + s;
+    }
+    koff[2 * slot] = a[q] * TT * 8;
+    koff[2 * slot + 1] = b[q] * TT * 8;
+  }
+  if ((e = alloc_copy((void **)&pl.koff, koff.data(), sizeof(int32_t) * koff.size())) != hipSuccess) return e;
+  pl.koff_tt = TT;
   const int nrt = Ppad / 32;
   if (pl.precision != MMNLSE_SPLIT_BF16) {
     const int nk = Ppad / 8;
