@@ -75,16 +75,19 @@ static void free_plan(Plan *pl) {
   delete pl;
 }
 
-// The RK4IP step of Eq. (6a-f) as five fused launches (nine when the FFT is
-// four-step), over the state A and two work fields:
+// The RK4IP step of Eq. (6a-f) as four fused launches (eight when the FFT is
+// four-step; five / nine for Kerr kernels without the fused K_23), over the
+// state A and two work fields:
 //   (pre)  W0 = h N(A)                                   k1 before dispersion
 //   F_a    A <- D A (=A_I),  W0 <- D W0 (=k1)            Eq. 6a, 6b
-//   K_2    W1 = h N(A_I + k1/2)                          Eq. 6c
-//   K_3    k3 = h N(A_I + k2/2); W0 <- A_I + k3;
+//   K_23   k2 = h N(A_I + k1/2)                          Eq. 6c
+//          k3 = h N(A_I + k2/2); W0 <- A_I + k3;
 //          W1 <- A_I + k1/6 + k2/3 + k3/3                Eq. 6d and the 6f sum
 //   F_b    W0 <- D W0,  W1 <- D W1                       Eq. 6e, 6f
 //   K_4    k4 = h N(W0); A <- W1 + k4/6                  Eq. 6e, 6f
 //          and, unless last, W0 = h N(A) for the next step.
+// k2 and k3 only need the same sample of every mode, so both evaluations fit
+// one launch; so do k4 and the next step's k1.
 hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float4 *E,
                      float2 *const *work, Prof *prof, bool start, bool finish) {
   if (n_steps <= 0) return hipSuccess;
@@ -94,7 +97,7 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
     if (prof && (e = prof->record(prof->kerr, pl.stream)) != hipSuccess) return e;
     if ((e = launch_kerr(pl, h, k)) != hipSuccess) return e;
     if (prof) {
-      prof->kerr_evals += (k.stage == STAGE_K4 && k.next) ? 2 : 1;
+      prof->kerr_evals += ((k.stage == STAGE_K4 && k.next) || k.stage == STAGE_K23) ? 2 : 1;
       return prof->record(prof->kerr, pl.stream);
     }
     return hipSuccess;
@@ -105,6 +108,30 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
     return prof ? prof->record(prof->lin, pl.stream) : hipSuccess;
   };
   KerrLaunch k{};
+  // k2 and k3 from X (A_I, or the state for the split-step) and k1 in W0:
+  // one fused launch where the Kerr kernel supports it, else two.
+  auto stages23 = [&](float2 *X) -> hipError_t {
+    k = KerrLaunch{};
+    k.src0 = X;
+    k.src1 = W0;
+    if (kerr_fuses_k23(pl.kerr_path)) {
+      k.stage = STAGE_K23;
+      k.out0 = W0;
+      k.out1 = W1;
+      return kerr(k);
+    }
+    k.stage = STAGE_K2;
+    k.out0 = W1;
+    if ((e = kerr(k)) != hipSuccess) return e;
+    k = KerrLaunch{};
+    k.stage = STAGE_K3;
+    k.src0 = X;
+    k.src1 = W0;
+    k.src2 = W1;
+    k.out0 = W0;
+    k.out1 = W1;
+    return kerr(k);
+  };
   if (pl.method == MMNLSE_SSFM_RK4) {
     // Eq. (4): D_half, RK4 over h on A' = N(A), D_half; the two half steps
     // between consecutive steps are one full step exp(h L) (table E2).
@@ -120,20 +147,8 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
       k.src0 = A;
       k.out0 = W0;
       if ((e = kerr(k)) != hipSuccess) return e;
-      k = KerrLaunch{};
-      k.stage = STAGE_K2;  // k2 = h N(A + k1/2)
-      k.src0 = A;
-      k.src1 = W0;
-      k.out0 = W1;
-      if ((e = kerr(k)) != hipSuccess) return e;
-      k = KerrLaunch{};
-      k.stage = STAGE_K3;  // k3; W0 <- A + k3, W1 <- A + k1/6 + k2/3 + k3/3
-      k.src0 = A;
-      k.src1 = W0;
-      k.src2 = W1;
-      k.out0 = W0;
-      k.out1 = W1;
-      if ((e = kerr(k)) != hipSuccess) return e;
+      // k2 = h N(A + k1/2), k3; W0 <- A + k3, W1 <- A + k1/6 + k2/3 + k3/3
+      if ((e = stages23(A)) != hipSuccess) return e;
       k = KerrLaunch{};
       k.stage = STAGE_K4;  // A <- W1 + h N(W0)/6
       k.src0 = W0;
@@ -154,20 +169,7 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
   }
   for (int64_t s = 0; s < n_steps; ++s) {
     if ((e = linear(A, W0)) != hipSuccess) return e;
-    k = KerrLaunch{};
-    k.stage = STAGE_K2;
-    k.src0 = A;
-    k.src1 = W0;
-    k.out0 = W1;
-    if ((e = kerr(k)) != hipSuccess) return e;
-    k = KerrLaunch{};
-    k.stage = STAGE_K3;
-    k.src0 = A;
-    k.src1 = W0;
-    k.src2 = W1;
-    k.out0 = W0;
-    k.out1 = W1;
-    if ((e = kerr(k)) != hipSuccess) return e;
+    if ((e = stages23(A)) != hipSuccess) return e;
     if ((e = linear(W0, W1)) != hipSuccess) return e;
     k = KerrLaunch{};
     k.stage = STAGE_K4;

@@ -63,7 +63,14 @@ enum KerrStage : int32_t {
   STAGE_K4 = 2,
   // X = src0 + src1/2 (A_I + k1/2); out0 = h N(X)
   STAGE_K2 = 3,
+  // STAGE_K2 then STAGE_K3 in one launch (both are pointwise in t):
+  // k2 = h N(src0 + src1/2), kept in out1; k3 = h N(src0 + k2/2);
+  // out0 = src0 + k3, out1 = src0 + src1/6 + k2/3 + k3/3 (out0 may be src1)
+  STAGE_K23 = 4,
 };
+
+// Kerr paths whose kernels implement STAGE_K23
+inline bool kerr_fuses_k23(KerrPath p) { return p == KERR_MFMA || p == KERR_SMALL; }
 
 struct KerrLaunch {
   KerrStage stage;

@@ -66,11 +66,30 @@ __global__ __launch_bounds__(256) void kerr_small(KArgs a) {
   for (int p = 0; p < M; ++p) {
     const size_t g = (size_t)p * a.T + t;
     float2 v = a.src0[g];
-    if (STAGE == STAGE_K2) v = caxpy(v, 0.5f, a.src1[g]);
+    if (STAGE == STAGE_K2 || STAGE == STAGE_K23) v = caxpy(v, 0.5f, a.src1[g]);
     if (STAGE == STAGE_K3) v = caxpy(v, 0.5f, a.src2[g]);
     x[p] = v;
   }
   eval_small<M>(a.Sg, a.hg, x, k);
+  if (STAGE == STAGE_K23) {  // k3 from A_I + k2/2; k2 stays in registers
+    float2 k2[M];
+#pragma unroll
+    for (int p = 0; p < M; ++p) {
+      k2[p] = k[p];
+      x[p] = caxpy(a.src0[(size_t)p * a.T + t], 0.5f, k2[p]);
+    }
+    eval_small<M>(a.Sg, a.hg, x, k);
+#pragma unroll
+    for (int p = 0; p < M; ++p) {
+      const size_t g = (size_t)p * a.T + t;
+      const float2 ai = a.src0[g], k1 = a.src1[g];
+      a.out0[g] = cadd(ai, k[p]);
+      float2 z = caxpy(ai, 1.f / 6.f, k1);
+      z = caxpy(z, 1.f / 3.f, k2[p]);
+      a.out1[g] = caxpy(z, 1.f / 3.f, k[p]);
+    }
+    return;
+  }
 #pragma unroll
   for (int p = 0; p < M; ++p) {
     const size_t g = (size_t)p * a.T + t;
@@ -262,6 +281,7 @@ hipError_t go_small(const KArgs &a, KerrStage st, hipStream_t s) {
     case STAGE_K2: hipLaunchKernelGGL((kerr_small<M, STAGE_K2>), grid, dim3(256), 0, s, a); break;
     case STAGE_K3: hipLaunchKernelGGL((kerr_small<M, STAGE_K3>), grid, dim3(256), 0, s, a); break;
     case STAGE_K4: hipLaunchKernelGGL((kerr_small<M, STAGE_K4>), grid, dim3(256), 0, s, a); break;
+    case STAGE_K23: hipLaunchKernelGGL((kerr_small<M, STAGE_K23>), grid, dim3(256), 0, s, a); break;
   }
   return hipGetLastError();
 }

@@ -363,7 +363,7 @@ __global__ __launch_bounds__(64 * W * R) void kerr_mfma(MArgs a) {
   for (int idx = threadIdx.x; idx < MT; idx += NT) {
     const size_t g = (size_t)(idx / TT) * a.T + t0 + (idx % TT);
     float2 v = a.src0[g];
-    if (STAGE == STAGE_K2) v = caxpy(v, 0.5f, a.src1[g]);
+    if (STAGE == STAGE_K2 || STAGE == STAGE_K23) v = caxpy(v, 0.5f, a.src1[g]);
     if (STAGE == STAGE_K3) v = caxpy(v, 0.5f, a.src2[g]);
     Xs[idx] = v;
   }
@@ -380,6 +380,9 @@ __global__ __launch_bounds__(64 * W * R) void kerr_mfma(MArgs a) {
     const float2 k = make_float2(-a.hg * o.y, a.hg * o.x);  // i h gamma sum
     if (STAGE == STAGE_PLAIN || STAGE == STAGE_K2) {
       a.out0[g] = k;
+    } else if (STAGE == STAGE_K23) {  // k2 -> out1 (read back below), next argument A_I + k2/2
+      a.out1[g] = k;
+      Xs[idx] = caxpy(a.src0[g], 0.5f, k);
     } else if (STAGE == STAGE_K3) {
       const float2 ai = a.src0[g], k1 = a.src1[g], k2 = a.src2[g];
       a.out0[g] = cadd(ai, k);
@@ -392,18 +395,28 @@ __global__ __launch_bounds__(64 * W * R) void kerr_mfma(MArgs a) {
       Xs[idx] = An;
     }
   }
-  if (STAGE == STAGE_K4 && a.next) {
+  if ((STAGE == STAGE_K4 && a.next) || STAGE == STAGE_K23) {
     __syncthreads();
     for (int idx = threadIdx.x; idx < R * MT; idx += NT) Os[idx] = make_float2(0.f, 0.f);
     __syncthreads();
     if (COOP) contract_coop<W, R>(a, Xs, Os + rg * MT, Bs, lane, col, cg, rg);
-  else contract<W, R, SPLIT, RTM>(a, Xs, Os + rg * MT, lane, col, rg);
+    else contract<W, R, SPLIT, RTM>(a, Xs, Os + rg * MT, lane, col, rg);
     __syncthreads();
     for (int idx = threadIdx.x; idx < MT; idx += NT) {
+      const size_t g = (size_t)(idx / TT) * a.T + t0 + (idx % TT);
       float2 o = Os[idx];
 #pragma unroll
       for (int r = 1; r < R; ++r) o = cadd(o, Os[r * MT + idx]);
-      a.out1[(size_t)(idx / TT) * a.T + t0 + (idx % TT)] = make_float2(-a.hg * o.y, a.hg * o.x);
+      const float2 k = make_float2(-a.hg * o.y, a.hg * o.x);
+      if (STAGE == STAGE_K23) {  // same thread wrote out1[g] (k2) above
+        const float2 ai = a.src0[g], k1 = a.src1[g], k2 = a.out1[g];
+        a.out0[g] = cadd(ai, k);
+        float2 z = caxpy(ai, 1.f / 6.f, k1);
+        z = caxpy(z, 1.f / 3.f, k2);
+        a.out1[g] = caxpy(z, 1.f / 3.f, k);
+      } else {
+        a.out1[g] = k;
+      }
     }
   }
 }
@@ -427,6 +440,7 @@ hipError_t go(const MArgs &a, KerrStage st, hipStream_t s) {
     case STAGE_K2: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K2, COOP>);
     case STAGE_K3: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K3, COOP>);
     case STAGE_K4: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K4, COOP>);
+    case STAGE_K23: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K23, COOP>);
   }
   return hipErrorInvalidValue;
 }
