@@ -1,0 +1,123 @@
+"""Edge and maximum sizes of the boundary, against the oracle or closed forms.
+
+  * the largest transforms (T = 2^18 .. 2^20: four-step with 512- and
+    1024-point passes);
+  * the matrix-core contraction in its two widest workgroup shapes, M = 126
+    (two row groups) and M = 256 (the largest M, one row group), with a
+    tensor that is a sum of K symmetric rank-1 terms,
+        S = sum_k c_k u_k (x) u_k (x) u_k (x) u_k,
+    for which N_p = i gamma sum_k c_k u_kp (u_k . X)^2 conj(u_k . X) in closed
+    form (the oracle's rank-1 pin), so no M^4 reference sum is needed;
+  * rows too short for the 128-sample workgroup (T = 64);
+  * zero steps.
+
+Tolerance of the wide contractions: the packed GEMM accumulates P = M(M+1)/2
+products per output in FP32, two per matrix-core step, so rounding grows like
+sqrt(P/2) * 6e-8: 3.8e-6 at M = 126 and 7.7e-6 at M = 256; the bars are about
+three times that.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def crandn(rng, *shape):
+    return ((rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / math.sqrt(2)).astype(np.complex64)
+
+
+@pytest.mark.parametrize("T", [2 ** 18, 2 ** 19, 2 ** 20])
+def test_linear_half_step_largest_T(gpu_lib, T):
+    mm = gpu_lib
+    import torch
+    M, dt = 2, 0.05
+    print(f"linear_half_step T={T}", flush=True)
+    rng = np.random.default_rng((23, T))
+    beta = np.column_stack([rng.uniform(-50, 50, M), rng.uniform(-20, 20, M), rng.uniform(-25, -15, M)])
+    S = W.symmetric_gaussian_tensor(M, rng).astype(np.float32)
+    P = mm.Propagator(M, T, dt, beta, S, 1.0, 0.1, 0.1)
+    X = crandn(rng, M, T)
+    Y = P.linear_half_step(torch.from_numpy(X).cuda()).cpu().numpy()
+    E = oracle.half_step_propagator(oracle.angular_frequencies(T, dt), beta, None, 0.1)
+    ref = oracle.apply_linear(X.astype(np.complex128), E)
+    err = rel(Y, ref)
+    print(f"  rel L2 = {err:.3e}", flush=True)
+    assert err < 1e-6
+    P.close()
+
+
+def _rank_k_tensor(M, rng, K=3):
+    u = rng.standard_normal((K, M)).astype(np.float32)
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    c = rng.uniform(0.5, 1.5, K).astype(np.float32)
+    S = np.zeros((M,) * 4, dtype=np.float32)
+    for k in range(K):
+        cube = np.einsum("l,m,n->lmn", u[k], u[k], u[k])
+        for p in range(M):   # one p-slab at a time keeps the temporaries at M^3
+            S[p] += (c[k] * u[k, p]) * cube
+    return S, u.astype(np.float64), c.astype(np.float64)
+
+
+@pytest.mark.parametrize("M,tol", [(126, 1.2e-5), (256, 2.5e-5)])
+def test_kerr_mfma_widest_shapes(gpu_lib, M, tol):
+    mm = gpu_lib
+    import torch
+    T, gamma, h = 256, 1.3, 0.05
+    print(f"kerr mfma M={M}: building the tensor", flush=True)
+    rng = np.random.default_rng((29, M))
+    S, u, c = _rank_k_tensor(M, rng)
+    beta = np.zeros((M, 1))
+    P = mm.Propagator(M, T, 0.5, beta, S, gamma, h, h, symmetric=True)
+    del S
+    assert P.kerr_path == "mfma"
+    X = crandn(rng, M, T)
+    Y = P.kerr(torch.from_numpy(X).cuda()).cpu().numpy()
+    Xd = X.astype(np.complex128)
+    y = u @ Xd                                         # [K, T]: u_k . X
+    ref = 1j * gamma * h * np.einsum("k,kp,kt->pt", c, u, y * y * np.conj(y))
+    err = rel(Y, ref)
+    print(f"  rel L2 = {err:.3e}", flush=True)
+    assert err < tol
+    P.close()
+
+
+def test_kerr_mfma_short_rows(gpu_lib):
+    """T = 64 is below the 128-sample workgroup: the 32-sample shape runs."""
+    mm = gpu_lib
+    import torch
+    M, T = 6, 64
+    rng = np.random.default_rng(31)
+    S = W.symmetric_gaussian_tensor(M, rng).astype(np.float32)
+    P = mm.Propagator(M, T, 0.5, np.zeros((M, 1)), S, 1.3, 0.05, 0.05)
+    assert P.kerr_path == "mfma"
+    X = crandn(rng, M, T)
+    Y = P.kerr(torch.from_numpy(X).cuda()).cpu().numpy()
+    ref = 0.05 * oracle.kerr_term(X.astype(np.complex128), S.astype(np.float64), 1.3)
+    assert rel(Y, ref) < 2e-6
+    P.close()
+
+
+def test_zero_steps_leave_the_field_unchanged(gpu_lib):
+    mm = gpu_lib
+    import torch
+    p = W.make_problem("qpsk6", T=2 ** 12, n_steps=1)
+    P = mm.Propagator.from_problem(p)
+    A = torch.from_numpy(p.A0).cuda()
+    P.advance(A, 0)
+    torch.cuda.synchronize()
+    assert np.array_equal(A.cpu().numpy(), p.A0)
+    with pytest.raises(mm.MMNLSEError):
+        P.advance(A, -1)
+    P.close()
