@@ -143,6 +143,12 @@ mmnlse_status mmnlse_propagate(mmnlse_t h, const void *A_in, void *A_out, int32_
 /* Advance a device-resident complex64 field A[M][T] in place by n_steps
  * RK4IP steps of size h (n_steps >= 0), asynchronously on the handle's
  * stream.  This is the hot path with no host transfer and no host sync.
+ * For fields of at most 2^20 samples (M*T), where a step is a few short
+ * kernels, the middle steps of calls with n_steps >= 18 run as replays of a
+ * HIP graph of 16 steps, captured by the first call that passes a given A
+ * (on an internal stream; replayed on the handle's stream) -- the same
+ * kernels in the same order, so the result is bit-identical to the eager
+ * schedule.  The environment variable MMNLSE_GRAPH=0 disables this.
  * Errors: E_INVALID, E_DEVICE (launch failure). */
 mmnlse_status mmnlse_advance(mmnlse_t h, void *A, int64_t n_steps);
 

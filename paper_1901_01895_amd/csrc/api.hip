@@ -72,6 +72,8 @@ static void free_plan(Plan *pl) {
   for (auto &b : pl->buf) hipFree(b);
   for (auto &b : pl->sd) hipFree(b);
   hipFree(pl->red);
+  if (pl->graph) hipGraphExecDestroy(pl->graph);
+  if (pl->cap_stream) hipStreamDestroy(pl->cap_stream);
   delete pl;
 }
 
@@ -181,6 +183,71 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
     if ((e = kerr(k)) != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+// Launch-bound plans (a field of at most 2^20 samples: a step is 4 to 8 short
+// kernels) replay their middle steps as a HIP graph of kGraphSteps steps,
+// captured once per field pointer, so the host pays one launch per chunk.
+// The graph holds exactly the kernels run_steps issues (no memset nodes), in
+// the same order with the same arguments, so results are bit-identical to
+// the eager schedule.  MMNLSE_GRAPH=0 turns it off.
+constexpr int kGraphSteps = 16;
+
+static bool graph_eligible(const Plan &pl) {
+  const char *env = std::getenv("MMNLSE_GRAPH");
+  if (env && env[0] == '0') return false;
+  return pl.method == MMNLSE_RK4IP && (size_t)pl.M * pl.T <= ((size_t)1 << 20);
+}
+
+static hipError_t capture_graph(Plan &pl, float2 *A) {
+  hipError_t e;
+  if (pl.graph) {
+    if ((e = hipGraphExecDestroy(pl.graph)) != hipSuccess) return e;
+    pl.graph = nullptr;
+    pl.graph_A = nullptr;
+  }
+  if (!pl.cap_stream && (e = hipStreamCreateWithFlags(&pl.cap_stream, hipStreamNonBlocking)) != hipSuccess)
+    return e;
+  hipStream_t user = pl.stream;
+  pl.stream = pl.cap_stream;  // the launch wrappers issue on pl.stream
+  hipGraph_t g = nullptr;
+  e = hipStreamBeginCapture(pl.cap_stream, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    const hipError_t er = run_steps(pl, A, kGraphSteps, pl.h, pl.E, pl.buf, nullptr, false, false);
+    e = hipStreamEndCapture(pl.cap_stream, &g);
+    if (er != hipSuccess) e = er;
+  }
+  pl.stream = user;
+  if (e == hipSuccess) e = hipGraphInstantiate(&pl.graph, g, nullptr, nullptr, 0);
+  if (g) hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    pl.graph = nullptr;
+    return e;
+  }
+  pl.graph_A = A;
+  pl.graph_steps = kGraphSteps;
+  return hipSuccess;
+}
+
+// n_steps of the fixed-step schedule on A: eager, or first step, graph
+// replays of the middle steps, and the remaining steps (the last one
+// without the look-ahead evaluation), which is the same launch sequence.
+// The graph for a field pointer is captured on the first call that passes
+// it, also a short one, so that a later long call on it only replays.
+static hipError_t advance_steps(Plan &pl, float2 *A, int64_t n_steps) {
+  if (n_steps > 0 && graph_eligible(pl) && !pl.graph_failed && pl.graph_A != A &&
+      capture_graph(pl, A) != hipSuccess) {
+    (void)hipGetLastError();
+    pl.graph_failed = true;
+  }
+  if (pl.graph_failed || pl.graph_A != A || !graph_eligible(pl) || n_steps < 2 + kGraphSteps)
+    return run_steps(pl, A, n_steps, pl.h, pl.E, pl.buf);
+  hipError_t e;
+  const int64_t k = (n_steps - 2) / kGraphSteps, tail = n_steps - 1 - k * kGraphSteps;
+  if ((e = run_steps(pl, A, 1, pl.h, pl.E, pl.buf, nullptr, true, false)) != hipSuccess) return e;
+  for (int64_t i = 0; i < k; ++i)
+    if ((e = hipGraphLaunch(pl.graph, pl.stream)) != hipSuccess) return e;
+  return run_steps(pl, A, tail, pl.h, pl.E, pl.buf, nullptr, false, true);
 }
 
 static bool check_symmetric(const float *S, int M, double tol, std::string &why) {
@@ -431,7 +498,7 @@ mmnlse_status mmnlse_advance(mmnlse_t h, void *A, int64_t n_steps) {
   if (!h || !A) return fail(MMNLSE_E_INVALID, "null argument");
   if (n_steps < 0) return fail(MMNLSE_E_INVALID, "n_steps < 0");
   Plan &pl = *h->pl;
-  hipError_t e = run_steps(pl, (float2 *)A, n_steps, pl.h, pl.E, pl.buf);
+  hipError_t e = advance_steps(pl, (float2 *)A, n_steps);
   if (e != hipSuccess) return hipfail(e, "advance");
   return MMNLSE_OK;
 }
@@ -472,7 +539,7 @@ mmnlse_status mmnlse_propagate(mmnlse_t h, const void *A_in, void *A_out, int32_
   HIPCHK(reduce_norms(pl, state, nullptr, MT, &p_in, nullptr), "power");
   if (!std::isfinite(p_in)) return fail(MMNLSE_E_NONFINITE, "input field is not finite");
   const auto t0 = std::chrono::steady_clock::now();
-  hipError_t e = run_steps(pl, state, pl.n_steps, pl.h, pl.E, pl.buf);
+  hipError_t e = advance_steps(pl, state, pl.n_steps);
   if (e == hipSuccess) e = hipStreamSynchronize(pl.stream);
   const auto t1 = std::chrono::steady_clock::now();
   if (e != hipSuccess) return hipfail(e, "steps");

@@ -120,6 +120,14 @@ struct Plan {
   int32_t *koff = nullptr;      // [Ppad][2] LDS byte offsets of (X_a, X_b) per q, kernel lane order
   int koff_tt = 0;              // tile width (samples) the offsets were built for
 
+  // replayed step graph for launch-bound plans: `graph_steps` middle RK4IP
+  // steps on the field at `graph_A`, captured on `cap_stream`
+  hipGraphExec_t graph = nullptr;
+  float2 *graph_A = nullptr;
+  int graph_steps = 0;
+  hipStream_t cap_stream = nullptr;
+  bool graph_failed = false;  // capture did not work here: stay eager
+
   // workspace
   float2 *buf[3] = {nullptr, nullptr, nullptr};
   float2 *sd[3] = {nullptr, nullptr, nullptr};  // step-doubling workspace (lazy)
