@@ -334,7 +334,7 @@ size_t estimate_plan_bytes(const mmnlse_config &cfg) {
                     (!(cfg.flags & MMNLSE_KERR_GENERIC) && cfg.M >= 3 && sym);
   if (mfma) {
     const size_t P = M * (M + 1) / 2, Ppad = (P + 63) / 64 * 64;
-    b += Ppad * Ppad * 4 + Ppad * 4;  // FP32, or bf16 hi + lo: 4 bytes per entry either way
+    b += Ppad * Ppad * 4 + Ppad * 12;  // FP32, or bf16 hi + lo: 4 bytes per entry either way; pair and offset tables
   } else {
     b += M * M * M * M * sizeof(float);
   }
