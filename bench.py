@@ -37,13 +37,17 @@ WORKLOADS = {
 }
 
 
-def kerr_flops_per_eval(M: int, T: int) -> float:
-    """Algorithmic flops of one Kerr evaluation h N(X) in the packed form:
-    B_q = X_l X_m (6 flops per pair and sample), C = S_pack B (real P x P
-    times complex P x T: 4 P^2 T), out_p = sum_n C_pn conj(X_n) (8 per (p,n)
-    term, M^2 terms per sample)."""
+def kerr_flops_per_eval(M: int, T: int, entries: float | None = None) -> float:
+    """Flops of one Kerr evaluation h N(X) in the packed form: B_q = X_l X_m
+    (6 flops per pair and sample), C = S_pack B (4 flops per packed tensor
+    entry and sample: a real multiply-add on Re B and on Im B), out_p =
+    sum_n C_pn conj(X_n) (8 per (p,n) term, M^2 terms per sample).
+    ``entries`` = packed tensor entries counted (default: all P^2; the
+    algorithmic count takes only the nonzero ones)."""
     P = M * (M + 1) // 2
-    return 4.0 * P * P * T + 6.0 * P * T + 8.0 * M * M * T
+    if entries is None:
+        entries = float(P * P)
+    return 4.0 * entries * T + 6.0 * P * T + 8.0 * M * M * T
 
 
 def linear_bytes_per_apply(M: int, T: int, four_step: bool) -> float:
@@ -287,12 +291,16 @@ def measure(mm, W, p, precision: str, args) -> dict:
     four = p.T > 16384
     kerr_avg_ms = prof["kerr_ms"] / max(prof["kerr_launches"], 1)
     lin_avg_ms = prof["linear_ms"] / max(prof["linear_launches"], 1)
-    kflops = kerr_flops_per_eval(p.M, p.T)
+    path = P.kerr_path
+    work = P.kerr_work() if path == "mfma" else None
+    # algorithmic: nonzero tensor entries only; executed: the blocks the kernel multiplies
+    kflops = kerr_flops_per_eval(p.M, p.T, work["nonzero"] if work else None)
+    xflops = kerr_flops_per_eval(p.M, p.T, work["multiplied"] if work else None)
     evals_per_launch = prof["kerr_evals"] / max(prof["kerr_launches"], 1)
     kerr_tflops = kflops * evals_per_launch / (kerr_avg_ms * 1e-3) / 1e12
+    exec_tflops = xflops * evals_per_launch / (kerr_avg_ms * 1e-3) / 1e12
     lin_gbs = 2 * linear_bytes_per_apply(p.M, p.T, four) / (lin_avg_ms * 1e-3) / 1e9
     kerr_dominant = prof["kerr_ms"] >= prof["linear_ms"]
-    path = P.kerr_path
     if kerr_dominant:
         if path == "mfma" and prec == mm.SPLIT_BF16:
             bound, peak = "mfma", BF16_PEAK_TFLOPS
@@ -304,7 +312,10 @@ def measure(mm, W, p, precision: str, args) -> dict:
         roof = {"bound": bound, "achieved": kerr_tflops, "peak": peak, "unit": "TFLOP/s",
                 "frac": kerr_tflops / peak, "traffic": traffic_for(kname, args.workload),
                 "kernel": kname, "avg_launch_ms": kerr_avg_ms,
-                "evals_per_launch": evals_per_launch}
+                "evals_per_launch": evals_per_launch,
+                "flops_per_eval": kflops, "executed_tflops": exec_tflops,
+                "nonzero_fraction": work["nonzero"] / work["dense"] if work else 1.0,
+                "multiplied_fraction": work["multiplied"] / work["dense"] if work else 1.0}
     else:
         kname = "linear_half_step"
         roof = {"bound": "hbm", "achieved": lin_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -312,7 +323,7 @@ def measure(mm, W, p, precision: str, args) -> dict:
                 "kernel": kname, "avg_launch_ms": lin_avg_ms}
     P.close()
     return {"value": value, "ms_per_step": ms_per_step, "roofline": roof, "kerr_kernel": path,
-            "kernels": {"kerr_ms_per_step": prof["kerr_ms"] / args.steps,
+            "kernels": {"kerr_ms_per_step": prof["kerr_ms"] / args.steps, "kerr_executed_tflops": exec_tflops,
                         "linear_ms_per_step": prof["linear_ms"] / args.steps,
                         "kerr_tflops": kerr_tflops, "linear_GBps": lin_gbs}}
 

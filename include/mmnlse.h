@@ -240,6 +240,16 @@ mmnlse_status mmnlse_synchronize(mmnlse_t h);
 /* Bytes of device memory the handle holds (workspace, tables, tensor). */
 mmnlse_status mmnlse_footprint(const mmnlse_t h, size_t *bytes);
 
+/* Work of one Kerr evaluation per time sample on the matrix-core path
+ * (E_UNSUPPORTED for the other paths), as counts of packed tensor entries:
+ * entries[0] = P*P (P = M(M+1)/2, the dense packed contraction),
+ * entries[1] = entries in the blocks the kernel multiplies (32 rows by one
+ * k-step, kept when they hold a nonzero entry; padding included),
+ * entries[2] = nonzero entries.  Each entry costs 4 flops per sample (a real
+ * multiply-add on the real and on the imaginary part of B_q).  Host array
+ * of 3 doubles. */
+mmnlse_status mmnlse_kerr_work(const mmnlse_t h, double *entries);
+
 /* Kernel used for the Kerr term: 0 = per-sample register kernel (M <= 8),
  * 1 = generic LDS kernel (any S), 2 = packed matrix-core contraction,
  * 3 = Manakov / XPM form of Eq. (1). */

@@ -29,7 +29,7 @@ SYMBOLS = (
     "mmnlse_create", "mmnlse_destroy", "mmnlse_last_error", "mmnlse_propagate", "mmnlse_advance",
     "mmnlse_linear_half_step", "mmnlse_kerr", "mmnlse_power", "mmnlse_step_doubling",
     "mmnlse_synchronize", "mmnlse_footprint", "mmnlse_kerr_path", "mmnlse_profile",
-    "mmnlse_propagate_adaptive",
+    "mmnlse_propagate_adaptive", "mmnlse_kerr_work",
     "mmnlse_server_create", "mmnlse_server_submit", "mmnlse_server_poll", "mmnlse_server_wait",
     "mmnlse_server_stats", "mmnlse_server_destroy",
 )
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mmnlse_synchronize.argtypes = [vp]
     lib.mmnlse_footprint.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
     lib.mmnlse_kerr_path.argtypes = [vp, ctypes.POINTER(i32)]
+    lib.mmnlse_kerr_work.argtypes = [vp, dp]
     lib.mmnlse_profile.argtypes = [vp, vp, i64, dp, ctypes.POINTER(ctypes.c_int64)]
     lib.mmnlse_propagate_adaptive.argtypes = [vp, vp, ctypes.POINTER(AdaptiveConfig), ctypes.POINTER(Trial),
                                               i64, ctypes.POINTER(AdaptiveResult)]
@@ -299,6 +300,13 @@ class Propagator:
             err.result, err.trials = out, trials
             raise err
         return out, trials
+
+    def kerr_work(self) -> dict:
+        """Packed-tensor entries per sample of one Kerr evaluation (matrix-core path):
+        dense P*P, multiplied (nonzero blocks), nonzero."""
+        out = (ctypes.c_double * 3)()
+        _check(load().mmnlse_kerr_work(self._h, out))
+        return {"dense": out[0], "multiplied": out[1], "nonzero": out[2]}
 
     def profile(self, A, n_steps: int) -> dict:
         """Advance A in place by n_steps with HIP events around every launch;

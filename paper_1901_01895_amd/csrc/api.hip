@@ -69,6 +69,8 @@ static void free_plan(Plan *pl) {
   hipFree(pl->Spl);
   hipFree(pl->pairs);
   hipFree(pl->koff);
+  hipFree(pl->passes);
+  hipFree(pl->klist);
   for (auto &b : pl->buf) hipFree(b);
   for (auto &b : pl->sd) hipFree(b);
   hipFree(pl->red);
@@ -759,6 +761,15 @@ mmnlse_status mmnlse_synchronize(mmnlse_t h) {
 mmnlse_status mmnlse_footprint(const mmnlse_t h, size_t *bytes) {
   if (!h || !bytes) return fail(MMNLSE_E_INVALID, "null argument");
   *bytes = h->pl->bytes;
+  return MMNLSE_OK;
+}
+
+mmnlse_status mmnlse_kerr_work(const mmnlse_t h, double *entries) {
+  g_err.clear();
+  if (!h || !entries) return fail(MMNLSE_E_INVALID, "null argument");
+  const Plan &pl = *h->pl;
+  if (pl.kerr_path != KERR_MFMA) return fail(MMNLSE_E_UNSUPPORTED, "work counts exist for the matrix-core path");
+  for (int i = 0; i < 3; ++i) entries[i] = pl.kerr_entries[i];
   return MMNLSE_OK;
 }
 

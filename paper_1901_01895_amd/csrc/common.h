@@ -119,6 +119,10 @@ struct Plan {
   int32_t *pairs = nullptr;     // [Ppad] packed (a | b << 16) for r / q index -> (a,b)
   int32_t *koff = nullptr;      // [Ppad][2] LDS byte offsets of (X_a, X_b) per q, kernel lane order
   int koff_tt = 0;              // tile width (samples) the offsets were built for
+  int4 *passes = nullptr;       // [npass] (first row tile, tiles, k-list offset, k-list length)
+  int32_t *klist = nullptr;     // nonzero k-steps of each pass
+  int npass = 0, mfma_rtm = 2;
+  double kerr_entries[3] = {0, 0, 0};  // packed P*P, multiplied (listed blocks), nonzero
 
   // replayed step graph for launch-bound plans: `graph_steps` middle RK4IP
   // steps on the field at `graph_A`, captured on `cap_stream`

@@ -21,8 +21,10 @@
 // v_mfma_f32_32x32x16_bf16, accumulated in FP32 (the lo*lo term, 2^-16 of
 // the product, is dropped).
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -40,8 +42,10 @@ struct MArgs {
   const uint4 *Ah, *Al;  // bf16 swizzle: [Ppad/32][Ppad/16][64] 8 x bf16
   const int *pairs;      // [Ppad] a | b << 16 (padding rows/cols -> (0,0), zero weight)
   const int4 *koff;      // B operand: byte offsets of X_a, X_b rows in the LDS tile, lane order
+  const int4 *passes;    // [npass] (first row tile, tiles, k-list offset, k-list length)
+  const int *klist;      // k-steps of each pass that hold a nonzero entry of its rows
   float hg;
-  int M, T, P, Ppad, next, koff_tt;
+  int M, T, P, Ppad, next, koff_tt, npass, rtm;
 };
 
 typedef float floatv2 __attribute__((ext_vector_type(2)));
@@ -118,9 +122,36 @@ __device__ __forceinline__ void scatter_tile(const MArgs &a, const floatx16 &cre
 // One pass over RT consecutive row tiles (rows 32*rt0 .. 32*(rt0+RT)-1) for
 // the wave's 32 samples: accumulate C over all q, then scatter into Os.  The
 // A operand of the next k-step is loaded while the current one is used.
+// A pass's k-list read through registers: lane i of `cur` holds entry 64c + i
+// of chunk c, `nxt` the following chunk (loaded 64 entries before it is
+// needed).  Entries come out with v_readlane, so the k-loop issues no scalar
+// memory loads (their counter is shared with LDS and would force full waits
+// on the B-operand reads).
+struct KList {
+  const int *kl;
+  int len, cur, nxt;
+  __device__ __forceinline__ int load(int c, int lane) const {
+    const int i = 64 * c + lane;
+    return i < len ? kl[i] : 0;
+  }
+  __device__ __forceinline__ void init(const int *k, int n, int lane) {
+    kl = k;
+    len = n;
+    cur = load(0, lane);
+    nxt = load(1, lane);
+  }
+  // entry i, i within the current chunk
+  __device__ __forceinline__ int at(int i) const { return __builtin_amdgcn_readlane(cur, i & 63); }
+  // call when the walk reaches entry i = 64c (c > 0): chunk c becomes current
+  __device__ __forceinline__ void advance(int i, int lane) {
+    cur = nxt;
+    nxt = load((i >> 6) + 1, lane);
+  }
+};
+
 template <int W, int RT, bool SPLIT>
 __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, float2 *Os, int lane, int col,
-                                              int rt0) {
+                                              int rt0, const int *kl, int len) {
   constexpr int TT = 32 * W;
   const int half = lane >> 5;
   const char *xb = (const char *)(Xs + col);
@@ -130,94 +161,127 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
     cre[j] = floatx16{0};
     cim[j] = floatx16{0};
   }
+  // The k-loop, for the k-steps kat(0..len-1).  A dense pass walks every
+  // k-step in order (kat is the identity, so addresses advance by a stride);
+  // a pass with zero blocks reads its list through registers.
   if (!SPLIT) {
-    const int nk = a.Ppad / 8;  // 4 k-steps of 2 per iteration
+    const int nk = a.Ppad / 8;  // 4 k-steps of 2 per iteration (a group of 8 columns)
     const float4 *Ab = a.A32 + (size_t)rt0 * nk * 64 + lane;
-    float4 av[RT], an[RT];
-#pragma unroll
-    for (int j = 0; j < RT; ++j) av[j] = Ab[(size_t)j * nk * 64];
-    // this lane half's (oa, ob) for the 4 k-steps of an iteration, one iteration ahead
+    // this lane half's (oa, ob) for the 4 k-steps of a group; the A operand
+    // and offsets of the next group are loaded one iteration ahead
     const int4 *ko = a.koff + 2 * half;
-    int4 o0 = ko[0], o1 = ko[1], on0 = o0, on1 = o1;
-    for (int kq = 0; kq < nk; ++kq) {
-      if (kq + 1 < nk) {
+    auto kloop = [&](auto kat) {
+      const int kq0 = kat(0);
+      float4 av[RT], an[RT];
 #pragma unroll
-        for (int j = 0; j < RT; ++j) an[j] = Ab[((size_t)j * nk + kq + 1) * 64];
-        on0 = ko[4 * (kq + 1)];
-        on1 = ko[4 * (kq + 1) + 1];
-      }
+      for (int j = 0; j < RT; ++j) an[j] = av[j] = Ab[((size_t)j * nk + kq0) * 64];
+      int4 o0 = ko[4 * kq0], o1 = ko[4 * kq0 + 1], on0 = o0, on1 = o1;
+      for (int it = 0; it < len; ++it) {
+        if (it + 1 < len) {
+          const int kn = kat(it + 1);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int oa = s == 0 ? o0.x : s == 1 ? o0.z : s == 2 ? o1.x : o1.z;
-        const int ob = s == 0 ? o0.y : s == 1 ? o0.w : s == 2 ? o1.y : o1.w;
-        const float2 b = form_b(xb, oa, ob);
-#pragma unroll
-        for (int j = 0; j < RT; ++j) {
-          const float av_s = s == 0 ? av[j].x : s == 1 ? av[j].y : s == 2 ? av[j].z : av[j].w;
-          cre[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, b.x, cre[j], 0, 0, 0);
-          cim[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, b.y, cim[j], 0, 0, 0);
+          for (int j = 0; j < RT; ++j) an[j] = Ab[((size_t)j * nk + kn) * 64];
+          on0 = ko[4 * kn];
+          on1 = ko[4 * kn + 1];
         }
-      }
 #pragma unroll
-      for (int j = 0; j < RT; ++j) av[j] = an[j];
-      o0 = on0;
-      o1 = on1;
+        for (int s = 0; s < 4; ++s) {
+          const int oa = s == 0 ? o0.x : s == 1 ? o0.z : s == 2 ? o1.x : o1.z;
+          const int ob = s == 0 ? o0.y : s == 1 ? o0.w : s == 2 ? o1.y : o1.w;
+          const float2 b = form_b(xb, oa, ob);
+#pragma unroll
+          for (int j = 0; j < RT; ++j) {
+            const float av_s = s == 0 ? av[j].x : s == 1 ? av[j].y : s == 2 ? av[j].z : av[j].w;
+            cre[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, b.x, cre[j], 0, 0, 0);
+            cim[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, b.y, cim[j], 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < RT; ++j) av[j] = an[j];
+        o0 = on0;
+        o1 = on1;
+      }
+    };
+    if (len == nk) {
+      kloop([](int i) { return i; });
+    } else {
+      KList L;
+      L.init(kl, len, lane);
+      kloop([&](int i) {
+        if (i > 0 && (i & 63) == 0) L.advance(i, lane);
+        return L.at(i);
+      });
     }
   } else {
     const int nk = a.Ppad / 16;  // k-steps of 16
     const uint4 *Hb = a.Ah + (size_t)rt0 * nk * 64 + lane;
     const uint4 *Lb = a.Al + (size_t)rt0 * nk * 64 + lane;
-    uint4 ah[RT], al[RT], ahn[RT], aln[RT];
-#pragma unroll
-    for (int j = 0; j < RT; ++j) {
-      ah[j] = Hb[(size_t)j * nk * 64];
-      al[j] = Lb[(size_t)j * nk * 64];
-    }
-    // this lane half's (oa, ob) for the 8 pairs of a k-step, one step ahead
+    // this lane half's (oa, ob) for the 8 pairs of a k-step; operands of the
+    // next k-step one iteration ahead
     const int4 *ko = a.koff + 4 * half;
-    int4 o[4], on[4];
+    auto kloop = [&](auto kat) {
+      const int ks0 = kat(0);
+      uint4 ah[RT], al[RT], ahn[RT], aln[RT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) on[i] = o[i] = ko[i];
-    for (int ks = 0; ks < nk; ++ks) {
-      if (ks + 1 < nk) {
+      for (int j = 0; j < RT; ++j) {
+        ahn[j] = ah[j] = Hb[((size_t)j * nk + ks0) * 64];
+        aln[j] = al[j] = Lb[((size_t)j * nk + ks0) * 64];
+      }
+      int4 o[4], on[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) on[i] = o[i] = ko[8 * ks0 + i];
+      for (int it = 0; it < len; ++it) {
+        if (it + 1 < len) {
+          const int kn = kat(it + 1);
+#pragma unroll
+          for (int j = 0; j < RT; ++j) {
+            ahn[j] = Hb[((size_t)j * nk + kn) * 64];
+            aln[j] = Lb[((size_t)j * nk + kn) * 64];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) on[i] = ko[8 * kn + i];
+        }
+        uint32_t urh[4], url[4], uih[4], uil[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {  // elements 2i and 2i+1
+          const float2 b0 = form_b(xb, o[i].x, o[i].y);
+          const float2 b1 = form_b(xb, o[i].z, o[i].w);
+          split2(b0.x, b1.x, urh[i], url[i]);
+          split2(b0.y, b1.y, uih[i], uil[i]);
+        }
+        const bf16x8 rh = __builtin_bit_cast(bf16x8, make_uint4(urh[0], urh[1], urh[2], urh[3]));
+        const bf16x8 rl = __builtin_bit_cast(bf16x8, make_uint4(url[0], url[1], url[2], url[3]));
+        const bf16x8 ih = __builtin_bit_cast(bf16x8, make_uint4(uih[0], uih[1], uih[2], uih[3]));
+        const bf16x8 il = __builtin_bit_cast(bf16x8, make_uint4(uil[0], uil[1], uil[2], uil[3]));
 #pragma unroll
         for (int j = 0; j < RT; ++j) {
-          ahn[j] = Hb[((size_t)j * nk + ks + 1) * 64];
-          aln[j] = Lb[((size_t)j * nk + ks + 1) * 64];
+          const bf16x8 sh = __builtin_bit_cast(bf16x8, ah[j]);
+          const bf16x8 sl = __builtin_bit_cast(bf16x8, al[j]);
+          cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, rh, cre[j], 0, 0, 0);
+          cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rl, cre[j], 0, 0, 0);
+          cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rh, cre[j], 0, 0, 0);
+          cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, ih, cim[j], 0, 0, 0);
+          cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, il, cim[j], 0, 0, 0);
+          cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, ih, cim[j], 0, 0, 0);
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) on[i] = ko[8 * (ks + 1) + i];
-      }
-      uint32_t urh[4], url[4], uih[4], uil[4];
+        for (int j = 0; j < RT; ++j) {
+          ah[j] = ahn[j];
+          al[j] = aln[j];
+        }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {  // elements 2i and 2i+1
-        const float2 b0 = form_b(xb, o[i].x, o[i].y);
-        const float2 b1 = form_b(xb, o[i].z, o[i].w);
-        split2(b0.x, b1.x, urh[i], url[i]);
-        split2(b0.y, b1.y, uih[i], uil[i]);
+        for (int i = 0; i < 4; ++i) o[i] = on[i];
       }
-      const bf16x8 rh = __builtin_bit_cast(bf16x8, make_uint4(urh[0], urh[1], urh[2], urh[3]));
-      const bf16x8 rl = __builtin_bit_cast(bf16x8, make_uint4(url[0], url[1], url[2], url[3]));
-      const bf16x8 ih = __builtin_bit_cast(bf16x8, make_uint4(uih[0], uih[1], uih[2], uih[3]));
-      const bf16x8 il = __builtin_bit_cast(bf16x8, make_uint4(uil[0], uil[1], uil[2], uil[3]));
-#pragma unroll
-      for (int j = 0; j < RT; ++j) {
-        const bf16x8 sh = __builtin_bit_cast(bf16x8, ah[j]);
-        const bf16x8 sl = __builtin_bit_cast(bf16x8, al[j]);
-        cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, rh, cre[j], 0, 0, 0);
-        cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rl, cre[j], 0, 0, 0);
-        cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rh, cre[j], 0, 0, 0);
-        cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, ih, cim[j], 0, 0, 0);
-        cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, il, cim[j], 0, 0, 0);
-        cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, ih, cim[j], 0, 0, 0);
-      }
-#pragma unroll
-      for (int j = 0; j < RT; ++j) {
-        ah[j] = ahn[j];
-        al[j] = aln[j];
-      }
-#pragma unroll
-      for (int i = 0; i < 4; ++i) o[i] = on[i];
+    };
+    if (len == nk) {
+      kloop([](int i) { return i; });
+    } else {
+      KList L;
+      L.init(kl, len, lane);
+      kloop([&](int i) {
+        if (i > 0 && (i & 63) == 0) L.advance(i, lane);
+        return L.at(i);
+      });
     }
   }
 #pragma unroll
@@ -324,22 +388,22 @@ __device__ __forceinline__ void contract_coop(const MArgs &a, const float2 *Xs, 
   }
 }
 
-// Full contraction for one wave: the row tiles are cut into passes of RTM
-// (remainder in passes of 2 and 1; rows are padded to a multiple of 32 only)
-// and pass i belongs to row group i % R.
+// Full contraction for one wave: the passes of the plan's pass table (runs of
+// 1, 2 or RTM row tiles chosen at setup; rows are padded to a multiple of 32
+// only) are dealt to the row groups, pass u to row group u % R.
+// A pass multiplies only the k-steps of its list (where its rows hold a
+// nonzero entry); a pass with an empty list contributes nothing.
 template <int W, int R, bool SPLIT, int RTM>
 __device__ __forceinline__ void contract(const MArgs &a, const float2 *Xs, float2 *Os, int lane, int col,
                                          int rg) {
-  const int nrt = a.Ppad / 32;
-  int rt0 = 0, unit = 0;
-  for (; rt0 + RTM <= nrt; rt0 += RTM, ++unit)
-    if (unit % R == rg) contract_pass<W, RTM, SPLIT>(a, Xs, Os, lane, col, rt0);
-  if (RTM > 2 && rt0 + 2 <= nrt) {
-    if (unit % R == rg) contract_pass<W, 2, SPLIT>(a, Xs, Os, lane, col, rt0);
-    rt0 += 2;
-    ++unit;
+  for (int u = rg; u < a.npass; u += R) {
+    const int4 ps = a.passes[u];
+    if (ps.w == 0) continue;
+    const int *kl = a.klist + ps.z;
+    if (RTM == 4 && ps.y == 4) contract_pass<W, (RTM == 4 ? 4 : 1), SPLIT>(a, Xs, Os, lane, col, ps.x, kl, ps.w);
+    else if (ps.y == 2) contract_pass<W, 2, SPLIT>(a, Xs, Os, lane, col, ps.x, kl, ps.w);
+    else contract_pass<W, 1, SPLIT>(a, Xs, Os, lane, col, ps.x, kl, ps.w);
   }
-  if (rt0 < nrt && unit % R == rg) contract_pass<W, 1, SPLIT>(a, Xs, Os, lane, col, rt0);
 }
 
 // Workgroup = W column groups x R row groups of waves.  Wave w owns the 32
@@ -478,14 +542,8 @@ hipError_t go_w(const MArgs &a, KerrStage st, hipStream_t s) {
     }();
     if (coop_env) return go_split_coop(a, st, s);
   }
-  // row tiles per pass: each pass forms B once and keeps 2*RTM accumulator
-  // tiles; MMNLSE_MFMA_RT (2 or 4) overrides the default for tuning runs
-  static const int rt_env = [] {
-    const char *e = std::getenv("MMNLSE_MFMA_RT");
-    return e ? std::atoi(e) : 0;
-  }();
-  const int rtm = rt_env == 2 || rt_env == 4 ? rt_env : 2;
-  if (rtm == 4) return go_shape<SPLIT, 4>(a, st, s);
+  // row tiles per pass (fixed when the pass table was built)
+  if (a.rtm == 4) return go_shape<SPLIT, 4>(a, st, s);
   return go_shape<SPLIT, 2>(a, st, s);
 }
 
@@ -519,6 +577,10 @@ hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k) {
   a.pairs = pl.pairs;
   a.koff = (const int4 *)pl.koff;
   a.koff_tt = pl.koff_tt;
+  a.passes = (const int4 *)pl.passes;
+  a.klist = pl.klist;
+  a.npass = pl.npass;
+  a.rtm = pl.mfma_rtm;
   a.hg = (float)(h * pl.gamma);
   a.M = pl.M;
   a.T = pl.T;
@@ -532,30 +594,59 @@ hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k) {
 hipError_t launch_pack_bf16(const Plan &) { return hipSuccess; }
 
 // Build the packed tensor, its pair table and the swizzled operand tables.
+//
+// Pairs are ordered so that rows with the same zero pattern over q are
+// adjacent (the same order is used for the columns): with a tensor whose
+// zeros follow mode groups, as in a fiber where whole groups of intermodal
+// terms vanish, whole 32-row x k-step blocks of Sp are then zero.  Each pass
+// (a run of row tiles that share one B fragment) gets the list of k-steps in
+// which its rows hold a nonzero entry, and multiplies only those.
 hipError_t setup_mfma(Plan &pl, const float *S) {
   const int M = pl.M;
   const int P = M * (M + 1) / 2;
   const int quantum = 32;  // one row tile; also a multiple of 16 (bf16 k-step) and 8
   const int Ppad = ((P + quantum - 1) / quantum) * quantum;
+  const bool split = pl.precision == MMNLSE_SPLIT_BF16;
   pl.P = P;
   pl.Ppad = Ppad;
-  std::vector<int> a(Ppad, 0), b(Ppad, 0);
-  std::vector<int32_t> pairs(Ppad, 0);
+  std::vector<int> na(P), nb(P);
   {
     int r = 0;
     for (int i = 0; i < M; ++i)
       for (int j = i; j < M; ++j, ++r) {
-        a[r] = i;
-        b[r] = j;
-        pairs[r] = i | (j << 16);
+        na[r] = i;
+        nb[r] = j;
       }
   }
-  // Sp[r][q] = w_q S[a_r, a_q, b_q, b_r]
-  auto Sp = [&](int r, int q) -> float {
-    if (r >= P || q >= P) return 0.f;
+  // Sp[r][q] = w_q S[a_r, a_q, b_q, b_r] for pairs in (a, b) order
+  auto entry = [&](const int *a, const int *b, int r, int q) -> float {
     const float w = a[q] < b[q] ? 2.f : 1.f;
     return w * S[(((size_t)a[r] * M + a[q]) * M + b[q]) * M + b[r]];
   };
+  const int words = (P + 63) / 64;
+  std::vector<uint64_t> mask((size_t)P * words, 0);
+  double nonzero = 0;
+  for (int r = 0; r < P; ++r)
+    for (int q = 0; q < P; ++q)
+      if (entry(na.data(), nb.data(), r, q) != 0.f) {
+        mask[(size_t)r * words + q / 64] |= 1ull << (q % 64);
+        nonzero += 1;
+      }
+  std::vector<int> perm(P);
+  for (int i = 0; i < P; ++i) perm[i] = i;
+  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) {
+    const uint64_t *mx = mask.data() + (size_t)x * words, *my = mask.data() + (size_t)y * words;
+    return std::lexicographical_compare(mx, mx + words, my, my + words);
+  });
+  std::vector<uint64_t>().swap(mask);
+  std::vector<int> a(Ppad, 0), b(Ppad, 0);
+  std::vector<int32_t> pairs(Ppad, 0);
+  for (int i = 0; i < P; ++i) {
+    a[i] = na[perm[i]];
+    b[i] = nb[perm[i]];
+    pairs[i] = a[i] | (b[i] << 16);
+  }
+  auto Sp = [&](int r, int q) -> float { return r < P && q < P ? entry(a.data(), b.data(), r, q) : 0.f; };
   hipError_t e;
   auto alloc_copy = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
     hipError_t r = hipMalloc(dst, bytes);
@@ -572,7 +663,7 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
   std::vector<int32_t> koff(2 * (size_t)Ppad);
   for (int q = 0; q < Ppad; ++q) {
     size_t slot = q;
-    if (pl.precision != MMNLSE_SPLIT_BF16) {
+    if (!split) {
       const int kq = q / 8, s = (q % 8) / 2, hf = q % 2;
       slot = ((size_t)kq * 2 + hf) * 4 + s;
     }
@@ -581,31 +672,103 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
   }
   if ((e = alloc_copy((void **)&pl.koff, koff.data(), sizeof(int32_t) * koff.size())) != hipSuccess) return e;
   pl.koff_tt = TT;
+  // swizzled A operand, and which (row tile, k-step) blocks hold a nonzero
   const int nrt = Ppad / 32;
-  if (pl.precision != MMNLSE_SPLIT_BF16) {
-    const int nk = Ppad / 8;
+  const int kw = split ? 16 : 8, nk = Ppad / kw;
+  std::vector<uint8_t> occ((size_t)nrt * nk, 0);
+  if (!split) {
     std::vector<float> sw((size_t)Ppad * Ppad);
     for (int rt = 0; rt < nrt; ++rt)
       for (int kq = 0; kq < nk; ++kq)
         for (int lane = 0; lane < 64; ++lane)
-          for (int s = 0; s < 4; ++s)
-            sw[(((size_t)rt * nk + kq) * 64 + lane) * 4 + s] = Sp(rt * 32 + (lane & 31), 8 * kq + 2 * s + (lane >> 5));
-    return alloc_copy((void **)&pl.Sp, sw.data(), sizeof(float) * sw.size());
+          for (int s = 0; s < 4; ++s) {
+            const float v = Sp(rt * 32 + (lane & 31), 8 * kq + 2 * s + (lane >> 5));
+            sw[(((size_t)rt * nk + kq) * 64 + lane) * 4 + s] = v;
+            if (v != 0.f) occ[(size_t)rt * nk + kq] = 1;
+          }
+    if ((e = alloc_copy((void **)&pl.Sp, sw.data(), sizeof(float) * sw.size())) != hipSuccess) return e;
+  } else {
+    std::vector<uint16_t> hi((size_t)Ppad * Ppad), lo((size_t)Ppad * Ppad);
+    for (int rt = 0; rt < nrt; ++rt)
+      for (int ks = 0; ks < nk; ++ks)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int e8 = 0; e8 < 8; ++e8) {
+            const float v = Sp(rt * 32 + (lane & 31), 16 * ks + 8 * (lane >> 5) + e8);
+            const uint16_t hb = bf16_bits(v);
+            const size_t idx = (((size_t)rt * nk + ks) * 64 + lane) * 8 + e8;
+            hi[idx] = hb;
+            lo[idx] = bf16_bits(v - bf16_value(hb));
+            if (v != 0.f) occ[(size_t)rt * nk + ks] = 1;
+          }
+    if ((e = alloc_copy((void **)&pl.Sph, hi.data(), sizeof(uint16_t) * hi.size())) != hipSuccess) return e;
+    if ((e = alloc_copy((void **)&pl.Spl, lo.data(), sizeof(uint16_t) * lo.size())) != hipSuccess) return e;
   }
-  const int nk = Ppad / 16;
-  std::vector<uint16_t> hi((size_t)Ppad * Ppad), lo((size_t)Ppad * Ppad);
-  for (int rt = 0; rt < nrt; ++rt)
-    for (int ks = 0; ks < nk; ++ks)
-      for (int lane = 0; lane < 64; ++lane)
-        for (int e8 = 0; e8 < 8; ++e8) {
-          const float v = Sp(rt * 32 + (lane & 31), 16 * ks + 8 * (lane >> 5) + e8);
-          const uint16_t hb = bf16_bits(v);
-          const size_t idx = (((size_t)rt * nk + ks) * 64 + lane) * 8 + e8;
-          hi[idx] = hb;
-          lo[idx] = bf16_bits(v - bf16_value(hb));
-        }
-  if ((e = alloc_copy((void **)&pl.Sph, hi.data(), sizeof(uint16_t) * hi.size())) != hipSuccess) return e;
-  return alloc_copy((void **)&pl.Spl, lo.data(), sizeof(uint16_t) * lo.size());
+  // passes of RTM row tiles (remainder in passes of 2 and 1) and their
+  // k-lists.  RTM = 4 halves the B formations per output row but needs 128
+  // accumulator registers, which costs the second wave per SIMD; that wave
+  // exists only for M <= 64 (two 128-sample workgroups fit one CU's LDS),
+  // so RTM = 2 there and 4 above (measured: 36 modes 4.5 vs 5.8 ms per step,
+  // 120 modes 1441 vs 1167).  MMNLSE_MFMA_RT=2 or 4 overrides (tuning runs).
+  const char *rt_env = std::getenv("MMNLSE_MFMA_RT");
+  const int rt_req = rt_env ? std::atoi(rt_env) : 0;
+  const int rtm = rt_req == 2 || rt_req == 4 ? rt_req : (M > 64 ? 4 : 2);
+  std::vector<int4> passes;
+  std::vector<int32_t> klist;
+  double executed = 0;
+  // listed k-steps of tiles rt0 .. rt0+nt-1 (union of their nonzero blocks)
+  auto union_len = [&](int rt0, int nt) {
+    int len = 0;
+    for (int k = 0; k < nk; ++k) {
+      bool any = false;
+      for (int t = 0; t < nt; ++t) any = any || occ[(size_t)(rt0 + t) * nk + k];
+      len += any;
+    }
+    return len;
+  };
+  auto add_pass = [&](int rt0, int nt) {
+    const int off = (int)klist.size();
+    for (int k = 0; k < nk; ++k) {
+      bool any = false;
+      for (int t = 0; t < nt; ++t) any = any || occ[(size_t)(rt0 + t) * nk + k];
+      if (any) klist.push_back(k);
+    }
+    const int len = (int)klist.size() - off;
+    passes.push_back(make_int4(rt0, nt, off, len));
+    executed += (double)nt * 32 * kw * len;
+  };
+  // Passes of 1, 2 or RTM tiles, chosen by a cost model in cycles per listed
+  // k-step of one wave: matrix-core time per tile (FP32: 8 32x32x2 products of
+  // 64 cycles; split: 6 32x32x16 products of 32) plus forming the B fragment
+  // once per pass (about 40 resp. 110 vector instructions of 4 cycles).  A
+  // pass shares B between its tiles but multiplies the union of their lists,
+  // so tiles with different zero patterns are better run alone.  Minimum
+  // total cost over the row tiles by dynamic programming.
+  const double mc = split ? 192.0 : 512.0, bc = split ? 440.0 : 160.0;
+  std::vector<double> best(nrt + 1, 0.0);
+  std::vector<int> take(nrt + 1, 1);
+  for (int i = 1; i <= nrt; ++i) {
+    best[i] = best[i - 1] + union_len(i - 1, 1) * (mc + bc);
+    for (int nt = 2; nt <= rtm; nt *= 2) {
+      if (i < nt) break;
+      const double c = best[i - nt] + union_len(i - nt, nt) * (nt * mc + bc);
+      if (c < best[i]) {
+        best[i] = c;
+        take[i] = nt;
+      }
+    }
+  }
+  std::vector<std::pair<int, int>> runs;
+  for (int i = nrt; i > 0; i -= take[i]) runs.push_back({i - take[i], take[i]});
+  for (auto it = runs.rbegin(); it != runs.rend(); ++it) add_pass(it->first, it->second);
+  if (klist.empty()) klist.push_back(0);
+  if ((e = alloc_copy((void **)&pl.passes, passes.data(), sizeof(int4) * passes.size())) != hipSuccess) return e;
+  if ((e = alloc_copy((void **)&pl.klist, klist.data(), sizeof(int32_t) * klist.size())) != hipSuccess) return e;
+  pl.npass = (int)passes.size();
+  pl.mfma_rtm = rtm;
+  pl.kerr_entries[0] = (double)P * P;
+  pl.kerr_entries[1] = executed;
+  pl.kerr_entries[2] = nonzero;
+  return hipSuccess;
 }
 
 }  // namespace mmnlse

@@ -121,3 +121,27 @@ def test_zero_steps_leave_the_field_unchanged(gpu_lib):
     with pytest.raises(mm.MMNLSEError):
         P.advance(A, -1)
     P.close()
+
+
+@pytest.mark.parametrize("name,kw", [("qpsk6", dict(T=2 ** 10, n_steps=1)), ("wdm36", dict(T=2 ** 10, n_steps=1))])
+def test_kerr_work_counts(gpu_lib, name, kw):
+    """The matrix-core path reports the packed entries it multiplies: all P^2
+    for a dense tensor; for the mode-group-masked wdm36 tensor the nonzero
+    count of the packed matrix Sp[(p,n)][(l,m)] = w S[p,l,m,n], and at least
+    that many multiplied."""
+    mm = gpu_lib
+    p = W.make_problem(name, **kw)
+    P = mm.Propagator.from_problem(p)
+    work = P.kerr_work()
+    M = p.M
+    pairs = [(i, j) for i in range(M) for j in range(i, M)]
+    a = np.array([x[0] for x in pairs])
+    b = np.array([x[1] for x in pairs])
+    Sp = p.S[a[:, None], a[None, :], b[None, :], b[:, None]]
+    nnz = int(np.count_nonzero(Sp))
+    print(f"{name}: dense {work['dense']:.0f}, multiplied {work['multiplied']:.0f}, nonzero {work['nonzero']:.0f}",
+          flush=True)
+    assert work["dense"] == len(pairs) ** 2
+    assert work["nonzero"] == nnz
+    assert nnz <= work["multiplied"] <= ((len(pairs) + 31) // 32 * 32) ** 2
+    P.close()
