@@ -634,10 +634,49 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
       }
   std::vector<int> perm(P);
   for (int i = 0; i < P; ++i) perm[i] = i;
+  auto row = [&](int r) { return mask.data() + (size_t)r * words; };
   std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) {
-    const uint64_t *mx = mask.data() + (size_t)x * words, *my = mask.data() + (size_t)y * words;
-    return std::lexicographical_compare(mx, mx + words, my, my + words);
+    return std::lexicographical_compare(row(x), row(x) + words, row(y), row(y) + words);
   });
+  // Rows with equal patterns now form groups.  A row tile that straddles two
+  // groups multiplies the union of their patterns, so neighbouring groups
+  // should be similar: order the groups greedily, each next group the one
+  // whose pattern is nearest (Hamming distance) to the last (skipped when
+  // that search would be too long).
+  {
+    std::vector<int> gs;
+    for (int i = 0; i < P; ++i)
+      if (i == 0 || !std::equal(row(perm[i]), row(perm[i]) + words, row(perm[i - 1]))) gs.push_back(i);
+    gs.push_back(P);
+    const int G = (int)gs.size() - 1;
+    if (G > 2 && (double)G * G * words <= 2e8) {
+      std::vector<char> used(G, 0);
+      std::vector<int> order{0};
+      used[0] = 1;
+      for (int n = 1; n < G; ++n) {
+        const uint64_t *cur = row(perm[gs[order.back()]]);
+        int best = -1;
+        long bestd = -1;
+        for (int g = 0; g < G; ++g) {
+          if (used[g]) continue;
+          const uint64_t *o = row(perm[gs[g]]);
+          long d = 0;
+          for (int w = 0; w < words; ++w) d += __builtin_popcountll(cur[w] ^ o[w]);
+          if (best < 0 || d < bestd) {
+            best = g;
+            bestd = d;
+          }
+        }
+        used[best] = 1;
+        order.push_back(best);
+      }
+      std::vector<int> p2;
+      p2.reserve(P);
+      for (int g : order)
+        for (int i = gs[g]; i < gs[g + 1]; ++i) p2.push_back(perm[i]);
+      perm.swap(p2);
+    }
+  }
   std::vector<uint64_t>().swap(mask);
   std::vector<int> a(Ppad, 0), b(Ppad, 0);
   std::vector<int32_t> pairs(Ppad, 0);
