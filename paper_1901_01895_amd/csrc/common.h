@@ -151,7 +151,6 @@ hipError_t launch_convert_c64_to_c128(const Plan &pl, const float2 *in, double2 
 // FP64 sum of |x|^2 (and of |x - y|^2 when y != nullptr) -> host values (synchronises)
 hipError_t reduce_norms(const Plan &pl, const float2 *x, const float2 *y, size_t n, double *sx,
                         double *sxy);
-hipError_t launch_pack_bf16(const Plan &pl);
 
 // optional per-launch event pairs (measurement only)
 struct Prof {

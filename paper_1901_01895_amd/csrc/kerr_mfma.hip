@@ -288,106 +288,6 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
   for (int j = 0; j < RT; ++j) scatter_tile<TT>(a, cre[j], cim[j], rt0 + j, Xs, Os, lane, col);
 }
 
-// Split path with cooperative B: the R waves of a column group form each
-// 16-pair k-step of B (hi and lo, real and imaginary parts) together into an
-// LDS buffer -- wave rg forms pairs rg*16/R .. (rg+1)*16/R-1 for the group's
-// 32 samples -- and all of them then read the whole fragment for their own
-// row tiles.  Row tiles go in units of two (one trailing unit of one when the
-// count is odd); unit u belongs to row group u % R, and all waves walk the
-// k-steps in lockstep (one barrier per k-step, double-buffered), including
-// waves whose row group has no unit left in the last round.
-template <int W, int R>
-__device__ __forceinline__ void contract_coop(const MArgs &a, const float2 *Xs, float2 *Os, uint16_t *Bs,
-                                              int lane, int col, int cg, int rg) {
-  constexpr int TT = 32 * W;
-  constexpr int QW = 16 / R;          // pairs each wave forms per k-step
-  constexpr int QL = QW / 2;          // pairs per lane (two lane halves)
-  constexpr int ARR = 32 * 16;        // one array: 32 samples x 16 pairs (bf16)
-  constexpr int BUF = W * 4 * ARR;    // one k-step: W groups x {re hi, re lo, im hi, im lo}
-  const int half = lane >> 5;
-  const int j = lane & 31;
-  const int nk = a.Ppad / 16;
-  const int nrt = a.Ppad / 32;
-  const int nunits = (nrt + 1) / 2;
-  const int rounds = (nunits + R - 1) / R;
-  for (int round = 0; round < rounds; ++round) {
-    const int u = round * R + rg;
-    const int rt0 = 2 * u;
-    const int ntiles = u < nunits ? (rt0 + 2 <= nrt ? 2 : 1) : 0;
-    floatx16 cre[2], cim[2];
-    cre[0] = cre[1] = cim[0] = cim[1] = floatx16{0};
-    const uint4 *Hb = a.Ah + (size_t)rt0 * nk * 64 + lane;
-    const uint4 *Lb = a.Al + (size_t)rt0 * nk * 64 + lane;
-    uint4 ah[2], al[2], ahn[2], aln[2];
-    if (ntiles > 0) {
-      ah[0] = Hb[0];
-      al[0] = Lb[0];
-    }
-    if (ntiles > 1) {
-      ah[1] = Hb[(size_t)nk * 64];
-      al[1] = Lb[(size_t)nk * 64];
-    }
-    for (int ks = 0; ks < nk; ++ks) {
-      if (ks + 1 < nk) {
-        if (ntiles > 0) {
-          ahn[0] = Hb[(size_t)(ks + 1) * 64];
-          aln[0] = Lb[(size_t)(ks + 1) * 64];
-        }
-        if (ntiles > 1) {
-          ahn[1] = Hb[((size_t)nk + ks + 1) * 64];
-          aln[1] = Lb[((size_t)nk + ks + 1) * 64];
-        }
-      }
-      // form this wave's share of the k-step
-      uint16_t *bs = Bs + (ks & 1) * BUF + cg * 4 * ARR;
-      const int k0 = rg * QW + half * QL;  // first pair (within the k-step) of this lane
-#pragma unroll
-      for (int e = 0; e < QL; ++e) {
-        const int ab = a.pairs[16 * ks + k0 + e];
-        const float2 xa = Xs[(ab & 0xffff) * TT + col];
-        const float2 xb = Xs[(ab >> 16) * TT + col];
-        const float bre = fmaf(xa.x, xb.x, -xa.y * xb.y);
-        const float bim = fmaf(xa.x, xb.y, xa.y * xb.x);
-        const __bf16 hr = (__bf16)bre, hi = (__bf16)bim;
-        const __bf16 lr = (__bf16)(bre - (float)hr), li = (__bf16)(bim - (float)hi);
-        const int o = j * 16 + k0 + e;
-        bs[o] = __builtin_bit_cast(uint16_t, hr);
-        bs[ARR + o] = __builtin_bit_cast(uint16_t, lr);
-        bs[2 * ARR + o] = __builtin_bit_cast(uint16_t, hi);
-        bs[3 * ARR + o] = __builtin_bit_cast(uint16_t, li);
-      }
-      __syncthreads();
-      if (ntiles > 0) {
-        const int o = j * 16 + 8 * half;
-        const bf16x8 rh = *(const bf16x8 *)(bs + o);
-        const bf16x8 rl = *(const bf16x8 *)(bs + ARR + o);
-        const bf16x8 ih = *(const bf16x8 *)(bs + 2 * ARR + o);
-        const bf16x8 il = *(const bf16x8 *)(bs + 3 * ARR + o);
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-          if (t < ntiles) {
-            const bf16x8 sh = __builtin_bit_cast(bf16x8, ah[t]);
-            const bf16x8 sl = __builtin_bit_cast(bf16x8, al[t]);
-            cre[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, rh, cre[t], 0, 0, 0);
-            cre[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rl, cre[t], 0, 0, 0);
-            cre[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rh, cre[t], 0, 0, 0);
-            cim[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, ih, cim[t], 0, 0, 0);
-            cim[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, il, cim[t], 0, 0, 0);
-            cim[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, ih, cim[t], 0, 0, 0);
-          }
-        }
-      }
-      ah[0] = ahn[0];
-      al[0] = aln[0];
-      ah[1] = ahn[1];
-      al[1] = aln[1];
-    }
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-      if (t < ntiles) scatter_tile<TT>(a, cre[t], cim[t], rt0 + t, Xs, Os, lane, col);
-  }
-}
-
 // Full contraction for one wave: the passes of the plan's pass table (runs of
 // 1, 2 or RTM row tiles chosen at setup; rows are padded to a multiple of 32
 // only) are dealt to the row groups, pass u to row group u % R.
@@ -410,7 +310,7 @@ __device__ __forceinline__ void contract(const MArgs &a, const float2 *Xs, float
 // samples of column group w % W and the passes of row group w / W, and
 // scatters into that row group's partial tile; the R partials are summed in
 // a fixed order, so the result does not depend on timing.
-template <int W, int R, bool SPLIT, int RTM, int STAGE, bool COOP>
+template <int W, int R, bool SPLIT, int RTM, int STAGE>
 __global__ __launch_bounds__(64 * W * R) void kerr_mfma(MArgs a) {
   constexpr int TT = 32 * W;
   constexpr int NT = 64 * W * R;
@@ -418,7 +318,6 @@ __global__ __launch_bounds__(64 * W * R) void kerr_mfma(MArgs a) {
   const int MT = a.M * TT;
   float2 *Xs = sh;
   float2 *Os = sh + MT;  // R partial tiles
-  uint16_t *Bs = (uint16_t *)(Os + R * MT);  // cooperative B buffers (COOP only)
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int cg = w % W, rg = w / W;
@@ -433,8 +332,7 @@ __global__ __launch_bounds__(64 * W * R) void kerr_mfma(MArgs a) {
   }
   for (int idx = threadIdx.x; idx < R * MT; idx += NT) Os[idx] = make_float2(0.f, 0.f);
   __syncthreads();
-  if (COOP) contract_coop<W, R>(a, Xs, Os + rg * MT, Bs, lane, col, cg, rg);
-  else contract<W, R, SPLIT, RTM>(a, Xs, Os + rg * MT, lane, col, rg);
+  contract<W, R, SPLIT, RTM>(a, Xs, Os + rg * MT, lane, col, rg);
   __syncthreads();
   for (int idx = threadIdx.x; idx < MT; idx += NT) {
     const size_t g = (size_t)(idx / TT) * a.T + t0 + (idx % TT);
@@ -463,8 +361,7 @@ __global__ __launch_bounds__(64 * W * R) void kerr_mfma(MArgs a) {
     __syncthreads();
     for (int idx = threadIdx.x; idx < R * MT; idx += NT) Os[idx] = make_float2(0.f, 0.f);
     __syncthreads();
-    if (COOP) contract_coop<W, R>(a, Xs, Os + rg * MT, Bs, lane, col, cg, rg);
-    else contract<W, R, SPLIT, RTM>(a, Xs, Os + rg * MT, lane, col, rg);
+    contract<W, R, SPLIT, RTM>(a, Xs, Os + rg * MT, lane, col, rg);
     __syncthreads();
     for (int idx = threadIdx.x; idx < MT; idx += NT) {
       const size_t g = (size_t)(idx / TT) * a.T + t0 + (idx % TT);
@@ -485,12 +382,12 @@ __global__ __launch_bounds__(64 * W * R) void kerr_mfma(MArgs a) {
   }
 }
 
-template <int W, int R, bool SPLIT, int RTM, bool COOP = false>
+template <int W, int R, bool SPLIT, int RTM>
 hipError_t go(const MArgs &a, KerrStage st, hipStream_t s) {
   constexpr int TT = 32 * W;
-  if (!COOP && a.koff_tt != TT) return hipErrorInvalidValue;  // offsets built for another tile width
+  if (a.koff_tt != TT) return hipErrorInvalidValue;  // offsets built for another tile width
   const dim3 grid(a.T / TT), block(64 * W * R);
-  const size_t shm = (size_t)(1 + R) * a.M * TT * sizeof(float2) + (COOP ? 2 * W * 4 * 32 * 16 * 2 : 0);
+  const size_t shm = (size_t)(1 + R) * a.M * TT * sizeof(float2);
   auto launch = [&](auto kern) -> hipError_t {
     if (shm > 65536) {
       hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -500,11 +397,11 @@ hipError_t go(const MArgs &a, KerrStage st, hipStream_t s) {
     return hipGetLastError();
   };
   switch (st) {
-    case STAGE_PLAIN: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_PLAIN, COOP>);
-    case STAGE_K2: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K2, COOP>);
-    case STAGE_K3: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K3, COOP>);
-    case STAGE_K4: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K4, COOP>);
-    case STAGE_K23: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K23, COOP>);
+    case STAGE_PLAIN: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_PLAIN>);
+    case STAGE_K2: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K2>);
+    case STAGE_K3: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K3>);
+    case STAGE_K4: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K4>);
+    case STAGE_K23: return launch(kerr_mfma<W, R, SPLIT, RTM, STAGE_K23>);
   }
   return hipErrorInvalidValue;
 }
@@ -522,26 +419,8 @@ hipError_t go_shape(const MArgs &a, KerrStage st, hipStream_t s) {
   return go<1, 1, SPLIT, RTM>(a, st, s);
 }
 
-// Split path with cooperative B (LDS: field tile, R partials, 2 x W x 4 KiB of B):
-//   M <= 64: 2 column groups x 2 row groups;  M <= 120: 1 x 4;  M <= 202: 1 x 2;
-//   M <= 256: 1 x 1.
-hipError_t go_split_coop(const MArgs &a, KerrStage st, hipStream_t s) {
-  if (a.M <= 64) return go<2, 2, true, 2, true>(a, st, s);
-  if (a.M <= 120) return go<1, 4, true, 2, true>(a, st, s);
-  if (a.M <= 202) return go<1, 2, true, 2, true>(a, st, s);
-  return go<1, 1, true, 2, true>(a, st, s);
-}
-
 template <bool SPLIT>
 hipError_t go_w(const MArgs &a, KerrStage st, hipStream_t s) {
-  if (SPLIT) {
-    // cooperative B (measured slower on wdm36: 3.7 vs 2.4 ms/step) stays opt-in
-    static const int coop_env = [] {
-      const char *e = std::getenv("MMNLSE_SPLIT_COOP");
-      return e ? std::atoi(e) : 0;
-    }();
-    if (coop_env) return go_split_coop(a, st, s);
-  }
   // row tiles per pass (fixed when the pass table was built)
   if (a.rtm == 4) return go_shape<SPLIT, 4>(a, st, s);
   return go_shape<SPLIT, 2>(a, st, s);
@@ -590,8 +469,6 @@ hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k) {
   if (pl.precision == MMNLSE_SPLIT_BF16) return go_w<true>(a, k.stage, pl.stream);
   return go_w<false>(a, k.stage, pl.stream);
 }
-
-hipError_t launch_pack_bf16(const Plan &) { return hipSuccess; }
 
 // Build the packed tensor, its pair table and the swizzled operand tables.
 //
