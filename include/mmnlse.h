@@ -100,13 +100,21 @@ typedef struct {
   const float *kappa;    /* [M][M] host array (row a, column b), used with
                             MMNLSE_KERR_MANAKOV, else ignored; copied */
   int32_t method;        /* mmnlse_method (0 = RK4IP) */
+  int32_t diag_every;    /* mmnlse_propagate: FP64 diagnostics every this many steps
+                            (power drift; for RK4IP also the step-doubling local-error
+                            estimate), 0 = only power at the end; >= 0 */
 } mmnlse_config;
 
 typedef struct {
   double power_in;       /* dt * sum |A_in|^2 in W ps, FP64 reduction on the device */
   double power_out;      /* same for the result */
-  double seconds;        /* wall time of the step loop (host clock, synchronised) */
+  double seconds;        /* wall time of the step loop (host clock, synchronised),
+                            diagnostics included */
   int64_t steps;         /* RK4IP steps taken */
+  double power_drift_max; /* max |P(z)/P(0) - 1| over the diagnostic points (diag_every > 0) */
+  double local_err_max;  /* max over the points of delta/15, delta the step-doubling estimate
+                            of mmnlse_step_doubling from the state there (RK4IP plans) */
+  int64_t diag_points;   /* diagnostic points taken (0 when diag_every == 0) */
 } mmnlse_stats;
 
 typedef struct mmnlse_ctx *mmnlse_t;
@@ -130,6 +138,9 @@ mmnlse_status mmnlse_destroy(mmnlse_t h);
 const char *mmnlse_last_error(void);
 
 /* Propagate over the configured length, L/h RK4IP steps (Eq. 6a-f).
+ * With cfg->diag_every = k > 0 the steps run in chunks of k (bit-identical to
+ * one run) and after each chunk the FP64 power and, for RK4IP plans, the
+ * step-doubling estimate are taken from the state (see mmnlse_stats).
  * A_in, A_out: [M][T] complex of type `dtype` (mmnlse_dtype); host pointers
  * when on_device == 0 (the call then copies, runs and synchronises), device
  * pointers when on_device != 0 (still synchronises before returning, so

@@ -49,6 +49,7 @@ class Config(ctypes.Structure):
         ("gamma", ctypes.c_double), ("h_km", ctypes.c_double), ("L_km", ctypes.c_double),
         ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
         ("kappa", ctypes.POINTER(ctypes.c_float)), ("method", ctypes.c_int32),
+        ("diag_every", ctypes.c_int32),
     ]
 
 
@@ -66,7 +67,9 @@ class ServerCounters(ctypes.Structure):
 
 class Stats(ctypes.Structure):
     _fields_ = [("power_in", ctypes.c_double), ("power_out", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("steps", ctypes.c_int64)]
+                ("seconds", ctypes.c_double), ("steps", ctypes.c_int64),
+                ("power_drift_max", ctypes.c_double), ("local_err_max", ctypes.c_double),
+                ("diag_points", ctypes.c_int64)]
 
 
 class AdaptiveConfig(ctypes.Structure):
@@ -141,7 +144,7 @@ def _dptr(x) -> int:
 
 
 def make_config(M, T, dt, beta, S, gamma, h, L, alpha=None, precision=FP32, symmetric=None,
-                generic=False, kappa=None, method=RK4IP):
+                generic=False, kappa=None, method=RK4IP, diag_every=0):
     """mmnlse_config for the arguments; returns (config, arrays it points into).
 
     With ``kappa`` ([M, M]) the paper's Manakov / XPM nonlinear operator of
@@ -165,16 +168,17 @@ def make_config(M, T, dt, beta, S, gamma, h, L, alpha=None, precision=FP32, symm
     cfg.gamma, cfg.h_km, cfg.L_km = float(gamma), float(h), float(L)
     cfg.precision = int(precision)
     cfg.method = int(method)
+    cfg.diag_every = int(diag_every)
     cfg.flags = ((S_SYMMETRIC if symmetric else 0) | (KERR_GENERIC if generic else 0)
                  | (KERR_MANAKOV if kappa is not None else 0))
     return cfg, (beta, S, alpha, kappa)
 
 
-def problem_config(p, precision=FP32, generic=False, L=None, method=RK4IP):
+def problem_config(p, precision=FP32, generic=False, L=None, method=RK4IP, diag_every=0):
     """mmnlse_config for a workloads.Problem."""
     return make_config(p.M, p.T, p.dt, p.beta, p.S, p.gamma, p.h, p.L if L is None else L,
                        p.alpha if np.any(p.alpha) else None, precision, p.symmetric, generic,
-                       getattr(p, "kappa", None), method)
+                       getattr(p, "kappa", None), method, diag_every)
 
 
 class Propagator:
@@ -186,11 +190,12 @@ class Propagator:
 
     def __init__(self, M: int, T: int, dt: float, beta, S, gamma: float, h: float, L: float,
                  alpha=None, precision: int = FP32, symmetric: bool | None = None,
-                 generic: bool = False, stream=None, kappa=None, method: int = RK4IP):
+                 generic: bool = False, stream=None, kappa=None, method: int = RK4IP,
+                 diag_every: int = 0):
         import torch
         lib = load()
         cfg, self._keep = make_config(M, T, dt, beta, S, gamma, h, L, alpha, precision, symmetric, generic,
-                                      kappa, method)
+                                      kappa, method, diag_every)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = ctypes.c_void_p()
         _check(lib.mmnlse_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
@@ -202,11 +207,11 @@ class Propagator:
 
     @classmethod
     def from_problem(cls, p, precision: int = FP32, generic: bool = False, L: float | None = None,
-                     stream=None, method: int = RK4IP):
+                     stream=None, method: int = RK4IP, diag_every: int = 0):
         return cls(p.M, p.T, p.dt, p.beta, p.S, p.gamma, p.h, p.L if L is None else L,
                    alpha=p.alpha if np.any(p.alpha) else None, precision=precision,
                    symmetric=p.symmetric, generic=generic, stream=stream,
-                   kappa=getattr(p, "kappa", None), method=method)
+                   kappa=getattr(p, "kappa", None), method=method, diag_every=diag_every)
 
     # ------------------------------------------------------------------
     def close(self):
@@ -249,7 +254,8 @@ class Propagator:
                                         ctypes.c_void_p(out.data_ptr()), dtype, 1, ctypes.byref(st)))
         if stats:
             return out, {"power_in": st.power_in, "power_out": st.power_out, "seconds": st.seconds,
-                         "steps": st.steps}
+                         "steps": st.steps, "power_drift_max": st.power_drift_max,
+                         "local_err_max": st.local_err_max, "diag_points": st.diag_points}
         return out
 
     def advance(self, A, n_steps: int):

@@ -304,6 +304,7 @@ mmnlse_status validate_config(const mmnlse_config &c, std::string &why) {
   if (std::fabs(ratio - std::round(ratio)) > 1e-9 * std::max(1.0, ratio)) return bad("L/h is not an integer");
   if (c.precision != MMNLSE_FP32 && c.precision != MMNLSE_SPLIT_BF16) return bad("unknown precision");
   if (c.method != MMNLSE_RK4IP && c.method != MMNLSE_SSFM_RK4) return bad("unknown method");
+  if (c.diag_every < 0) return bad("diag_every < 0");
   for (int i = 0; i < M * c.n_beta; ++i)
     if (!std::isfinite(c.beta[i])) return bad("beta is not finite");
   if (c.alpha)
@@ -347,6 +348,8 @@ size_t estimate_plan_bytes(const mmnlse_config &cfg) {
 
 using namespace mmnlse;
 
+static mmnlse_status step_doubling_delta(Plan &pl, const void *X, double *delta);
+
 extern "C" {
 
 const char *mmnlse_last_error(void) { return g_err.c_str(); }
@@ -377,6 +380,7 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
   pl->n_beta = cfg->n_beta;
   pl->precision = cfg->precision;
   pl->method = cfg->method;
+  pl->diag_every = cfg->diag_every;
   pl->flags = cfg->flags;
   pl->stream = (hipStream_t)stream;
   hipGetDevice(&pl->device);
@@ -541,7 +545,28 @@ mmnlse_status mmnlse_propagate(mmnlse_t h, const void *A_in, void *A_out, int32_
   HIPCHK(reduce_norms(pl, state, nullptr, MT, &p_in, nullptr), "power");
   if (!std::isfinite(p_in)) return fail(MMNLSE_E_NONFINITE, "input field is not finite");
   const auto t0 = std::chrono::steady_clock::now();
-  hipError_t e = advance_steps(pl, state, pl.n_steps);
+  double drift_max = 0, err_max = 0;
+  int64_t points = 0;
+  hipError_t e = hipSuccess;
+  if (pl.diag_every > 0) {
+    for (int64_t done = 0; done < pl.n_steps && e == hipSuccess;) {
+      const int64_t c = std::min<int64_t>(pl.diag_every, pl.n_steps - done);
+      if ((e = advance_steps(pl, state, c)) != hipSuccess) break;
+      done += c;
+      double p = 0;
+      if ((e = reduce_norms(pl, state, nullptr, MT, &p, nullptr)) != hipSuccess) break;
+      drift_max = std::max(drift_max, std::fabs(p / p_in - 1.0));
+      if (pl.method == MMNLSE_RK4IP) {
+        double d = 0;
+        const mmnlse_status s2 = step_doubling_delta(pl, state, &d);
+        if (s2 != MMNLSE_OK) return s2;
+        err_max = std::max(err_max, d / 15.0);
+      }
+      ++points;
+    }
+  } else {
+    e = advance_steps(pl, state, pl.n_steps);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(pl.stream);
   const auto t1 = std::chrono::steady_clock::now();
   if (e != hipSuccess) return hipfail(e, "steps");
@@ -563,6 +588,9 @@ mmnlse_status mmnlse_propagate(mmnlse_t h, const void *A_in, void *A_out, int32_
     st->power_out = p_out;
     st->seconds = std::chrono::duration<double>(t1 - t0).count();
     st->steps = pl.n_steps;
+    st->power_drift_max = drift_max;
+    st->local_err_max = err_max;
+    st->diag_points = points;
   }
   if (!std::isfinite(p_out)) return fail(MMNLSE_E_NONFINITE, "result is not finite");
   return MMNLSE_OK;
@@ -602,10 +630,7 @@ mmnlse_status mmnlse_power(mmnlse_t h, const void *X, double *out) {
   return MMNLSE_OK;
 }
 
-mmnlse_status mmnlse_step_doubling(mmnlse_t h, const void *X, double *delta) {
-  g_err.clear();
-  if (!h || !X || !delta) return fail(MMNLSE_E_INVALID, "null argument");
-  Plan &pl = *h->pl;
+static mmnlse_status step_doubling_delta(Plan &pl, const void *X, double *delta) {
   if (pl.method != MMNLSE_RK4IP) return fail(MMNLSE_E_UNSUPPORTED, "step doubling is implemented for RK4IP plans");
   const size_t MT = (size_t)pl.M * pl.T;
   hipError_t e;
@@ -631,6 +656,12 @@ mmnlse_status mmnlse_step_doubling(mmnlse_t h, const void *X, double *delta) {
   HIPCHK(reduce_norms(pl, fine, coarse, MT, &sf, &sd), "norms");
   *delta = sf > 0 ? std::sqrt(sd / sf) : 0.0;
   return MMNLSE_OK;
+}
+
+mmnlse_status mmnlse_step_doubling(mmnlse_t h, const void *X, double *delta) {
+  g_err.clear();
+  if (!h || !X || !delta) return fail(MMNLSE_E_INVALID, "null argument");
+  return step_doubling_delta(*h->pl, X, delta);
 }
 
 // Step-doubling control (the paper steps with a fixed h; the exponent 1/5 is

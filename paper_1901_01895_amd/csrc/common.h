@@ -87,6 +87,7 @@ struct Plan {
   int n_beta = 0;
   int precision = MMNLSE_FP32;
   int method = MMNLSE_RK4IP;
+  int diag_every = 0;  // propagate: diagnostics every this many steps (0 = end only)
   uint32_t flags = 0;
   KerrPath kerr_path = KERR_GENERIC;
   // FFT decomposition: single pass in LDS when !four_step, else T = N1 * N2

@@ -251,6 +251,7 @@ mmnlse_status poll_impl(mmnlse_server *s, uint64_t ticket, void *A_out, mmnlse_s
   const mmnlse_status status = r->status;
   if (status == MMNLSE_OK && A_out) std::memcpy(A_out, r->out.data(), r->out.size());
   if (st) {
+    *st = mmnlse_stats{};
     st->power_in = r->p_in;
     st->power_out = r->p_out;
     st->seconds = std::chrono::duration<double>(r->t_done - r->t_start).count();

@@ -281,3 +281,38 @@ def test_ssfm_rk4_propagation(gpu_lib, name, kw):
     torch.cuda.synchronize()
     assert np.array_equal(host(A), out)
     P.close()
+
+
+def test_propagate_periodic_diagnostics(gpu_lib):
+    """diag_every = 64 on a third-order soliton over one period (256 steps): four
+    diagnostic points, a result bit-identical to the undiagnosed run, and the
+    largest power drift and step-doubling estimate (delta/15) equal to the
+    oracle's at the same four states.  At this coarse step both are scheme
+    error (drift ~4e-4, delta up to ~8e-3), far above the FP32 rounding."""
+    mm = gpu_lib
+    p = W.soliton_problem(T=1024, noise=0.0)
+    A0 = (3.0 * p.A0).astype(np.complex64)
+    z0 = math.pi / 2 * p.meta["T0"] ** 2 / abs(p.beta[0, 2])
+    n, every = 256, 64
+    P = mm.Propagator(1, p.T, p.dt, p.beta, p.S, p.gamma, z0 / n, z0, diag_every=every)
+    out, st = P.propagate(A0, stats=True)
+    Q = mm.Propagator(1, p.T, p.dt, p.beta, p.S, p.gamma, z0 / n, z0)
+    ref_gpu, st0 = Q.propagate(A0, stats=True)
+    assert st["diag_points"] == n // every and st0["diag_points"] == 0
+    assert np.array_equal(out, ref_gpu)
+    A = A0.astype(np.complex128)
+    p0 = oracle.power(A, p.dt)
+    est, drift = [], []
+    for _ in range(n // every):
+        A = oracle.propagate(A, p.beta, None, p.S, p.gamma, p.dt, z0 / n, every)
+        d, _ = oracle.step_doubling_estimate(A, p.beta, None, p.S, p.gamma, p.dt, z0 / n)
+        est.append(d / 15.0)
+        drift.append(abs(oracle.power(A, p.dt) / p0 - 1.0))
+    print(f"power drift: GPU {st['power_drift_max']:.4e}, oracle {max(drift):.4e}; "
+          f"local error estimate: GPU {st['local_err_max']:.4e}, oracle {max(est):.4e}", flush=True)
+    assert st["power_drift_max"] == pytest.approx(max(drift), rel=0.02)
+    assert st["local_err_max"] == pytest.approx(max(est), rel=0.05)
+    P.close()
+    Q.close()
+    with pytest.raises(mm.MMNLSEError):
+        mm.Propagator(1, p.T, p.dt, p.beta, p.S, p.gamma, z0 / n, z0, diag_every=-1)
