@@ -795,6 +795,37 @@ mmnlse_status mmnlse_footprint(const mmnlse_t h, size_t *bytes) {
   return MMNLSE_OK;
 }
 
+mmnlse_status mmnlse_kerr_plan(const float *S, int32_t M, int32_t precision, int32_t *counts, int32_t *perm,
+                               int32_t *passes, int32_t *klist, double *entries) {
+  g_err.clear();
+  if (!S || !counts) return fail(MMNLSE_E_INVALID, "null argument");
+  if (M < 1 || M > 256) return fail(MMNLSE_E_INVALID, "M must be in 1..256");
+  if (precision != MMNLSE_FP32 && precision != MMNLSE_SPLIT_BF16) return fail(MMNLSE_E_INVALID, "unknown precision");
+  KerrPlan kp;
+  try {
+    plan_kerr(S, M, precision == MMNLSE_SPLIT_BF16, kp);
+  } catch (const std::bad_alloc &) {
+    return fail(MMNLSE_E_NOMEM, "host allocation");
+  }
+  counts[0] = kp.P;
+  counts[1] = kp.Ppad;
+  counts[2] = (int32_t)kp.passes.size();
+  counts[3] = (int32_t)kp.klist.size();
+  counts[4] = kp.kw;
+  counts[5] = kp.rtm;
+  if (perm) std::copy(kp.perm.begin(), kp.perm.end(), perm);
+  for (size_t i = 0; passes && i < kp.passes.size(); ++i) {
+    passes[4 * i] = kp.passes[i].x;
+    passes[4 * i + 1] = kp.passes[i].y;
+    passes[4 * i + 2] = kp.passes[i].z;
+    passes[4 * i + 3] = kp.passes[i].w;
+  }
+  if (klist) std::copy(kp.klist.begin(), kp.klist.end(), klist);
+  if (entries)
+    for (int i = 0; i < 3; ++i) entries[i] = kp.entries[i];
+  return MMNLSE_OK;
+}
+
 mmnlse_status mmnlse_kerr_work(const mmnlse_t h, double *entries) {
   g_err.clear();
   if (!h || !entries) return fail(MMNLSE_E_INVALID, "null argument");

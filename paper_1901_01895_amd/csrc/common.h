@@ -141,6 +141,20 @@ struct Plan {
   size_t bytes = 0;
 };
 
+// Host-side plan of the packed matrix-core contraction (kerr_plan.hip).
+struct KerrPlan {
+  int P = 0, Ppad = 0, kw = 8, nk = 0, nrt = 0, rtm = 2;
+  std::vector<int> perm;             // [P] natural pair index at each position
+  std::vector<int> a, b;             // [Ppad] pair (a <= b) at each position, padding (0, 0)
+  std::vector<int4> passes;          // (first row tile, tiles, k-list offset, k-list length)
+  std::vector<int32_t> klist;        // k-steps of each pass that hold a nonzero
+  double entries[3] = {0, 0, 0};     // packed P*P, multiplied, nonzero
+};
+void plan_kerr(const float *S, int M, bool split, KerrPlan &kp);
+float packed_entry(const float *S, int M, int ar, int br, int aq, int bq);
+// samples per workgroup of the matrix-core kernel for M modes and T samples
+int mfma_tile_width(int M, int T);
+
 // kernels (launch wrappers); all asynchronous on plan.stream
 hipError_t launch_linear(const Plan &pl, const float4 *E, const float2 *in0, float2 *out0,
                          const float2 *in1, float2 *out1);

@@ -69,10 +69,6 @@ __device__ __forceinline__ float2 form_b(const char *xb, int oa, int ob) {
   return make_float2(fmaf(xa.x, xc.x, -xa.y * xc.y), fmaf(xa.x, xc.y, xa.y * xc.x));
 }
 
-// Samples per workgroup (32 W) of the shape go_shape picks for M modes and T
-// samples; the contraction's offset table is built for it.
-int mfma_tile_width(int M, int T) { return M <= 64 && T % 128 == 0 ? 128 : 32; }
-
 // Output row of accumulator register v for lane-half `half` of a 32x32 tile.
 __device__ __forceinline__ int acc_row(int v, int half) { return 8 * (v >> 2) + 4 * half + (v & 3); }
 
@@ -470,99 +466,21 @@ hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k) {
   return go_w<false>(a, k.stage, pl.stream);
 }
 
-// Build the packed tensor, its pair table and the swizzled operand tables.
-//
-// Pairs are ordered so that rows with the same zero pattern over q are
-// adjacent (the same order is used for the columns): with a tensor whose
-// zeros follow mode groups, as in a fiber where whole groups of intermodal
-// terms vanish, whole 32-row x k-step blocks of Sp are then zero.  Each pass
-// (a run of row tiles that share one B fragment) gets the list of k-steps in
-// which its rows hold a nonzero entry, and multiplies only those.
+// Build the device tables of the contraction from its host plan: the pair
+// table, the B-operand offsets, the swizzled A operand, the passes and
+// their k-lists.
 hipError_t setup_mfma(Plan &pl, const float *S) {
   const int M = pl.M;
-  const int P = M * (M + 1) / 2;
-  const int quantum = 32;  // one row tile; also a multiple of 16 (bf16 k-step) and 8
-  const int Ppad = ((P + quantum - 1) / quantum) * quantum;
   const bool split = pl.precision == MMNLSE_SPLIT_BF16;
+  KerrPlan kp;
+  plan_kerr(S, M, split, kp);
+  const int P = kp.P, Ppad = kp.Ppad, nrt = kp.nrt, nk = kp.nk;
   pl.P = P;
   pl.Ppad = Ppad;
-  std::vector<int> na(P), nb(P);
-  {
-    int r = 0;
-    for (int i = 0; i < M; ++i)
-      for (int j = i; j < M; ++j, ++r) {
-        na[r] = i;
-        nb[r] = j;
-      }
-  }
-  // Sp[r][q] = w_q S[a_r, a_q, b_q, b_r] for pairs in (a, b) order
-  auto entry = [&](const int *a, const int *b, int r, int q) -> float {
-    const float w = a[q] < b[q] ? 2.f : 1.f;
-    return w * S[(((size_t)a[r] * M + a[q]) * M + b[q]) * M + b[r]];
-  };
-  const int words = (P + 63) / 64;
-  std::vector<uint64_t> mask((size_t)P * words, 0);
-  double nonzero = 0;
-  for (int r = 0; r < P; ++r)
-    for (int q = 0; q < P; ++q)
-      if (entry(na.data(), nb.data(), r, q) != 0.f) {
-        mask[(size_t)r * words + q / 64] |= 1ull << (q % 64);
-        nonzero += 1;
-      }
-  std::vector<int> perm(P);
-  for (int i = 0; i < P; ++i) perm[i] = i;
-  auto row = [&](int r) { return mask.data() + (size_t)r * words; };
-  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) {
-    return std::lexicographical_compare(row(x), row(x) + words, row(y), row(y) + words);
-  });
-  // Rows with equal patterns now form groups.  A row tile that straddles two
-  // groups multiplies the union of their patterns, so neighbouring groups
-  // should be similar: order the groups greedily, each next group the one
-  // whose pattern is nearest (Hamming distance) to the last (skipped when
-  // that search would be too long).
-  {
-    std::vector<int> gs;
-    for (int i = 0; i < P; ++i)
-      if (i == 0 || !std::equal(row(perm[i]), row(perm[i]) + words, row(perm[i - 1]))) gs.push_back(i);
-    gs.push_back(P);
-    const int G = (int)gs.size() - 1;
-    if (G > 2 && (double)G * G * words <= 2e8) {
-      std::vector<char> used(G, 0);
-      std::vector<int> order{0};
-      used[0] = 1;
-      for (int n = 1; n < G; ++n) {
-        const uint64_t *cur = row(perm[gs[order.back()]]);
-        int best = -1;
-        long bestd = -1;
-        for (int g = 0; g < G; ++g) {
-          if (used[g]) continue;
-          const uint64_t *o = row(perm[gs[g]]);
-          long d = 0;
-          for (int w = 0; w < words; ++w) d += __builtin_popcountll(cur[w] ^ o[w]);
-          if (best < 0 || d < bestd) {
-            best = g;
-            bestd = d;
-          }
-        }
-        used[best] = 1;
-        order.push_back(best);
-      }
-      std::vector<int> p2;
-      p2.reserve(P);
-      for (int g : order)
-        for (int i = gs[g]; i < gs[g + 1]; ++i) p2.push_back(perm[i]);
-      perm.swap(p2);
-    }
-  }
-  std::vector<uint64_t>().swap(mask);
-  std::vector<int> a(Ppad, 0), b(Ppad, 0);
+  const int *a = kp.a.data(), *b = kp.b.data();
   std::vector<int32_t> pairs(Ppad, 0);
-  for (int i = 0; i < P; ++i) {
-    a[i] = na[perm[i]];
-    b[i] = nb[perm[i]];
-    pairs[i] = a[i] | (b[i] << 16);
-  }
-  auto Sp = [&](int r, int q) -> float { return r < P && q < P ? entry(a.data(), b.data(), r, q) : 0.f; };
+  for (int i = 0; i < P; ++i) pairs[i] = a[i] | (b[i] << 16);
+  auto Sp = [&](int r, int q) -> float { return r < P && q < P ? packed_entry(S, M, a[r], b[r], a[q], b[q]) : 0.f; };
   hipError_t e;
   auto alloc_copy = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
     hipError_t r = hipMalloc(dst, bytes);
@@ -588,20 +506,14 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
   }
   if ((e = alloc_copy((void **)&pl.koff, koff.data(), sizeof(int32_t) * koff.size())) != hipSuccess) return e;
   pl.koff_tt = TT;
-  // swizzled A operand, and which (row tile, k-step) blocks hold a nonzero
-  const int nrt = Ppad / 32;
-  const int kw = split ? 16 : 8, nk = Ppad / kw;
-  std::vector<uint8_t> occ((size_t)nrt * nk, 0);
+  // swizzled A operand: each lane's MFMA A fragment of a (row tile, k-step) in one 16-byte load
   if (!split) {
     std::vector<float> sw((size_t)Ppad * Ppad);
     for (int rt = 0; rt < nrt; ++rt)
       for (int kq = 0; kq < nk; ++kq)
         for (int lane = 0; lane < 64; ++lane)
-          for (int s = 0; s < 4; ++s) {
-            const float v = Sp(rt * 32 + (lane & 31), 8 * kq + 2 * s + (lane >> 5));
-            sw[(((size_t)rt * nk + kq) * 64 + lane) * 4 + s] = v;
-            if (v != 0.f) occ[(size_t)rt * nk + kq] = 1;
-          }
+          for (int s = 0; s < 4; ++s)
+            sw[(((size_t)rt * nk + kq) * 64 + lane) * 4 + s] = Sp(rt * 32 + (lane & 31), 8 * kq + 2 * s + (lane >> 5));
     if ((e = alloc_copy((void **)&pl.Sp, sw.data(), sizeof(float) * sw.size())) != hipSuccess) return e;
   } else {
     std::vector<uint16_t> hi((size_t)Ppad * Ppad), lo((size_t)Ppad * Ppad);
@@ -614,76 +526,18 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
             const size_t idx = (((size_t)rt * nk + ks) * 64 + lane) * 8 + e8;
             hi[idx] = hb;
             lo[idx] = bf16_bits(v - bf16_value(hb));
-            if (v != 0.f) occ[(size_t)rt * nk + ks] = 1;
           }
     if ((e = alloc_copy((void **)&pl.Sph, hi.data(), sizeof(uint16_t) * hi.size())) != hipSuccess) return e;
     if ((e = alloc_copy((void **)&pl.Spl, lo.data(), sizeof(uint16_t) * lo.size())) != hipSuccess) return e;
   }
-  // passes of RTM row tiles (remainder in passes of 2 and 1) and their
-  // k-lists.  RTM = 4 halves the B formations per output row but needs 128
-  // accumulator registers, which costs the second wave per SIMD; that wave
-  // exists only for M <= 64 (two 128-sample workgroups fit one CU's LDS),
-  // so RTM = 2 there and 4 above (measured: 36 modes 4.5 vs 5.8 ms per step,
-  // 120 modes 1441 vs 1167).  MMNLSE_MFMA_RT=2 or 4 overrides (tuning runs).
-  const char *rt_env = std::getenv("MMNLSE_MFMA_RT");
-  const int rt_req = rt_env ? std::atoi(rt_env) : 0;
-  const int rtm = rt_req == 2 || rt_req == 4 ? rt_req : (M > 64 ? 4 : 2);
-  std::vector<int4> passes;
-  std::vector<int32_t> klist;
-  double executed = 0;
-  // listed k-steps of tiles rt0 .. rt0+nt-1 (union of their nonzero blocks)
-  auto union_len = [&](int rt0, int nt) {
-    int len = 0;
-    for (int k = 0; k < nk; ++k) {
-      bool any = false;
-      for (int t = 0; t < nt; ++t) any = any || occ[(size_t)(rt0 + t) * nk + k];
-      len += any;
-    }
-    return len;
-  };
-  auto add_pass = [&](int rt0, int nt) {
-    const int off = (int)klist.size();
-    for (int k = 0; k < nk; ++k) {
-      bool any = false;
-      for (int t = 0; t < nt; ++t) any = any || occ[(size_t)(rt0 + t) * nk + k];
-      if (any) klist.push_back(k);
-    }
-    const int len = (int)klist.size() - off;
-    passes.push_back(make_int4(rt0, nt, off, len));
-    executed += (double)nt * 32 * kw * len;
-  };
-  // Passes of 1, 2 or RTM tiles, chosen by a cost model in cycles per listed
-  // k-step of one wave: matrix-core time per tile (FP32: 8 32x32x2 products of
-  // 64 cycles; split: 6 32x32x16 products of 32) plus forming the B fragment
-  // once per pass (about 40 resp. 110 vector instructions of 4 cycles).  A
-  // pass shares B between its tiles but multiplies the union of their lists,
-  // so tiles with different zero patterns are better run alone.  Minimum
-  // total cost over the row tiles by dynamic programming.
-  const double mc = split ? 192.0 : 512.0, bc = split ? 440.0 : 160.0;
-  std::vector<double> best(nrt + 1, 0.0);
-  std::vector<int> take(nrt + 1, 1);
-  for (int i = 1; i <= nrt; ++i) {
-    best[i] = best[i - 1] + union_len(i - 1, 1) * (mc + bc);
-    for (int nt = 2; nt <= rtm; nt *= 2) {
-      if (i < nt) break;
-      const double c = best[i - nt] + union_len(i - nt, nt) * (nt * mc + bc);
-      if (c < best[i]) {
-        best[i] = c;
-        take[i] = nt;
-      }
-    }
-  }
-  std::vector<std::pair<int, int>> runs;
-  for (int i = nrt; i > 0; i -= take[i]) runs.push_back({i - take[i], take[i]});
-  for (auto it = runs.rbegin(); it != runs.rend(); ++it) add_pass(it->first, it->second);
+  std::vector<int32_t> klist = kp.klist;
   if (klist.empty()) klist.push_back(0);
-  if ((e = alloc_copy((void **)&pl.passes, passes.data(), sizeof(int4) * passes.size())) != hipSuccess) return e;
+  if ((e = alloc_copy((void **)&pl.passes, kp.passes.data(), sizeof(int4) * kp.passes.size())) != hipSuccess)
+    return e;
   if ((e = alloc_copy((void **)&pl.klist, klist.data(), sizeof(int32_t) * klist.size())) != hipSuccess) return e;
-  pl.npass = (int)passes.size();
-  pl.mfma_rtm = rtm;
-  pl.kerr_entries[0] = (double)P * P;
-  pl.kerr_entries[1] = executed;
-  pl.kerr_entries[2] = nonzero;
+  pl.npass = (int)kp.passes.size();
+  pl.mfma_rtm = kp.rtm;
+  for (int i = 0; i < 3; ++i) pl.kerr_entries[i] = kp.entries[i];
   return hipSuccess;
 }
 

@@ -1,0 +1,182 @@
+// Host-side plan of the packed matrix-core Kerr contraction (no device
+// code): the order of the pairs, the zero blocks of the packed tensor, and
+// the passes of row tiles with the k-steps each of them multiplies.
+// setup_mfma builds the device tables from it; mmnlse_kerr_plan returns it
+// without a device.
+//
+// Packed form (symmetric S): rows r = (p <= n), columns q = (l <= m),
+// Sp[r][q] = w_q S[p, l, m, n] with w_q = 2 for l < m.  Rows are sorted by
+// their zero pattern over q (equal patterns adjacent), the groups of equal
+// rows chained greedily by Hamming distance, and the same order is used for
+// the columns.  A block of 32 rows x one k-step (8 columns FP32, 16 split)
+// is multiplied only when it holds a nonzero entry.
+
+#include <algorithm>
+#include <cstdlib>
+#include <utility>
+#include <vector>
+
+#include "common.h"
+
+namespace mmnlse {
+
+int mfma_tile_width(int M, int T) { return M <= 64 && T % 128 == 0 ? 128 : 32; }
+
+float packed_entry(const float *S, int M, int ar, int br, int aq, int bq) {
+  const float w = aq < bq ? 2.f : 1.f;
+  return w * S[(((size_t)ar * M + aq) * M + bq) * M + br];
+}
+
+void plan_kerr(const float *S, int M, bool split, KerrPlan &kp) {
+  const int P = M * (M + 1) / 2;
+  const int Ppad = (P + 31) / 32 * 32;  // one row tile; a multiple of the 8 and 16 column k-steps
+  kp.P = P;
+  kp.Ppad = Ppad;
+  kp.kw = split ? 16 : 8;
+  kp.nk = Ppad / kp.kw;
+  kp.nrt = Ppad / 32;
+  std::vector<int> na(P), nb(P);
+  {
+    int r = 0;
+    for (int i = 0; i < M; ++i)
+      for (int j = i; j < M; ++j, ++r) {
+        na[r] = i;
+        nb[r] = j;
+      }
+  }
+  // zero pattern of every row over the natural column order
+  const int words = (P + 63) / 64;
+  std::vector<uint64_t> mask((size_t)P * words, 0);
+  double nonzero = 0;
+  for (int r = 0; r < P; ++r)
+    for (int q = 0; q < P; ++q)
+      if (packed_entry(S, M, na[r], nb[r], na[q], nb[q]) != 0.f) {
+        mask[(size_t)r * words + q / 64] |= 1ull << (q % 64);
+        nonzero += 1;
+      }
+  auto row = [&](int r) { return mask.data() + (size_t)r * words; };
+  std::vector<int> perm(P);
+  for (int i = 0; i < P; ++i) perm[i] = i;
+  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) {
+    return std::lexicographical_compare(row(x), row(x) + words, row(y), row(y) + words);
+  });
+  // A row tile that straddles two groups of equal rows multiplies the union
+  // of their patterns, so neighbouring groups should be similar: chain the
+  // groups greedily, each next group the one nearest (Hamming distance) to
+  // the last (skipped when that search would be too long).
+  {
+    std::vector<int> gs;
+    for (int i = 0; i < P; ++i)
+      if (i == 0 || !std::equal(row(perm[i]), row(perm[i]) + words, row(perm[i - 1]))) gs.push_back(i);
+    gs.push_back(P);
+    const int G = (int)gs.size() - 1;
+    if (G > 2 && (double)G * G * words <= 2e8) {
+      std::vector<char> used(G, 0);
+      std::vector<int> order{0};
+      used[0] = 1;
+      for (int n = 1; n < G; ++n) {
+        const uint64_t *cur = row(perm[gs[order.back()]]);
+        int best = -1;
+        long bestd = -1;
+        for (int g = 0; g < G; ++g) {
+          if (used[g]) continue;
+          const uint64_t *o = row(perm[gs[g]]);
+          long d = 0;
+          for (int w = 0; w < words; ++w) d += __builtin_popcountll(cur[w] ^ o[w]);
+          if (best < 0 || d < bestd) {
+            best = g;
+            bestd = d;
+          }
+        }
+        used[best] = 1;
+        order.push_back(best);
+      }
+      std::vector<int> p2;
+      p2.reserve(P);
+      for (int g : order)
+        for (int i = gs[g]; i < gs[g + 1]; ++i) p2.push_back(perm[i]);
+      perm.swap(p2);
+    }
+  }
+  kp.perm = perm;
+  kp.a.assign(Ppad, 0);
+  kp.b.assign(Ppad, 0);
+  std::vector<int> inv(P);
+  for (int i = 0; i < P; ++i) {
+    kp.a[i] = na[perm[i]];
+    kp.b[i] = nb[perm[i]];
+    inv[perm[i]] = i;
+  }
+  // blocks (row tile, k-step) of the permuted matrix that hold a nonzero
+  const int nk = kp.nk, kw = kp.kw, nrt = kp.nrt;
+  std::vector<uint8_t> occ((size_t)nrt * nk, 0);
+  for (int rp = 0; rp < P; ++rp) {
+    const uint64_t *m = row(perm[rp]);
+    uint8_t *o = occ.data() + (size_t)(rp / 32) * nk;
+    for (int w = 0; w < words; ++w)
+      for (uint64_t bits = m[w]; bits; bits &= bits - 1) {
+        const int q = 64 * w + __builtin_ctzll(bits);
+        o[inv[q] / kw] = 1;
+      }
+  }
+  std::vector<uint64_t>().swap(mask);
+  // Row tiles per pass.  RTM = 4 halves the B formations per output row but
+  // needs 128 accumulator registers, which costs the second wave per SIMD;
+  // that wave exists only for M <= 64 (two 128-sample workgroups fit one
+  // CU's LDS), so RTM = 2 there and 4 above (measured: 36 modes 4.5 vs 5.8 ms
+  // per step, 120 modes 1441 vs 1167).  MMNLSE_MFMA_RT=2 or 4 overrides.
+  const char *rt_env = std::getenv("MMNLSE_MFMA_RT");
+  const int rt_req = rt_env ? std::atoi(rt_env) : 0;
+  const int rtm = rt_req == 2 || rt_req == 4 ? rt_req : (M > 64 ? 4 : 2);
+  kp.rtm = rtm;
+  // listed k-steps of tiles rt0 .. rt0+nt-1 (union of their nonzero blocks)
+  auto listed = [&](int rt0, int nt, std::vector<int32_t> *out) {
+    int len = 0;
+    for (int k = 0; k < nk; ++k) {
+      bool any = false;
+      for (int t = 0; t < nt; ++t) any = any || occ[(size_t)(rt0 + t) * nk + k];
+      if (any) {
+        ++len;
+        if (out) out->push_back(k);
+      }
+    }
+    return len;
+  };
+  // Passes of 1, 2 or RTM tiles, chosen by a cost model in cycles per listed
+  // k-step of one wave: matrix-core time per tile (FP32: 8 32x32x2 products of
+  // 64 cycles; split: 6 32x32x16 products of 32) plus forming the B fragment
+  // once per pass (about 40 resp. 110 vector instructions of 4 cycles).  A
+  // pass shares B between its tiles but multiplies the union of their lists,
+  // so tiles with different zero patterns are better run alone.  Minimum
+  // total cost over the row tiles by dynamic programming.
+  const double mc = split ? 192.0 : 512.0, bc = split ? 440.0 : 160.0;
+  std::vector<double> best(nrt + 1, 0.0);
+  std::vector<int> take(nrt + 1, 1);
+  for (int i = 1; i <= nrt; ++i) {
+    best[i] = best[i - 1] + listed(i - 1, 1, nullptr) * (mc + bc);
+    for (int nt = 2; nt <= rtm; nt *= 2) {
+      if (i < nt) break;
+      const double c = best[i - nt] + listed(i - nt, nt, nullptr) * (nt * mc + bc);
+      if (c < best[i]) {
+        best[i] = c;
+        take[i] = nt;
+      }
+    }
+  }
+  std::vector<std::pair<int, int>> runs;
+  for (int i = nrt; i > 0; i -= take[i]) runs.push_back({i - take[i], take[i]});
+  kp.passes.clear();
+  kp.klist.clear();
+  double executed = 0;
+  for (auto it = runs.rbegin(); it != runs.rend(); ++it) {
+    const int off = (int)kp.klist.size();
+    const int len = listed(it->first, it->second, &kp.klist);
+    kp.passes.push_back(make_int4(it->first, it->second, off, len));
+    executed += (double)it->second * 32 * kw * len;
+  }
+  kp.entries[0] = (double)P * P;
+  kp.entries[1] = executed;
+  kp.entries[2] = nonzero;
+}
+
+}  // namespace mmnlse

@@ -1,0 +1,122 @@
+"""Host-only plan of the matrix-core Kerr contraction (mmnlse_kerr_plan, CPU).
+
+The contraction multiplies only the (32-row tile, k-step) blocks listed for
+each pass.  These tests check the plan against the packed tensor computed
+here from its definition, Sp[(p,n)][(l,m)] = w S[p,l,m,n] (w = 2 for l < m):
+every nonzero entry must fall in a listed block of the pass that holds its
+row, passes must cover every row tile once, and the reported counts must
+match.  A planted mistake (one nonzero block dropped from the lists) must be
+caught by the same check.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+LIB = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                   "paper_1901_01895_amd", "libmmnlse.so")
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+
+
+def packed(S):
+    M = S.shape[0]
+    pairs = [(i, j) for i in range(M) for j in range(i, M)]
+    a = np.array([x[0] for x in pairs])
+    b = np.array([x[1] for x in pairs])
+    w = np.where(a < b, 2.0, 1.0)
+    return w[None, :] * S.astype(np.float64)[a[:, None], a[None, :], b[None, :], b[:, None]]
+
+
+def uncovered(plan, Sp):
+    """Nonzero entries of the permuted packed matrix outside every listed block."""
+    perm, kw, P = plan["perm"], plan["kw"], plan["P"]
+    X = Sp[np.ix_(perm, perm)]
+    listed = np.zeros((plan["Ppad"] // 32, plan["Ppad"] // kw), bool)
+    for rt0, nt, off, n in plan["passes"]:
+        for k in plan["klist"][off:off + n]:
+            listed[rt0:rt0 + nt, k] = True
+    rows, cols = np.nonzero(X)
+    return int(np.count_nonzero(~listed[rows // 32, cols // kw]))
+
+
+def check(plan, Sp):
+    P, kw = plan["P"], plan["kw"]
+    assert sorted(plan["perm"].tolist()) == list(range(P))
+    tiles = np.zeros(plan["Ppad"] // 32, int)
+    for rt0, nt, off, n in plan["passes"]:
+        tiles[rt0:rt0 + nt] += 1
+        ks = plan["klist"][off:off + n]
+        assert np.all(np.diff(ks) > 0) and (n == 0 or (ks[0] >= 0 and ks[-1] < plan["Ppad"] // kw))
+        assert nt in (1, 2, 4) and nt <= plan["rtm"]
+    assert np.all(tiles == 1)
+    assert uncovered(plan, Sp) == 0
+    e = plan["entries"]
+    assert e["dense"] == P * P
+    assert e["nonzero"] == np.count_nonzero(Sp)
+    assert e["multiplied"] == sum(nt * 32 * kw * n for _, nt, _, n in plan["passes"])
+    assert e["nonzero"] <= e["multiplied"] <= plan["Ppad"] ** 2
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_dense_tensor_keeps_natural_order_and_full_lists(precision):
+    import paper_1901_01895_amd as mm
+    S = W.symmetric_gaussian_tensor(6, np.random.default_rng(41)).astype(np.float32)
+    plan = mm.kerr_plan(S, precision)
+    Sp = packed(S)
+    check(plan, Sp)
+    assert np.array_equal(plan["perm"], np.arange(plan["P"]))
+    # every k-step holding a real column is listed; all-padding k-steps are not
+    nk_real = -(-plan["P"] // plan["kw"])
+    assert all(n == nk_real for _, _, _, n in plan["passes"])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_mode_group_masked_tensor_skips_only_zero_blocks(precision):
+    import paper_1901_01895_amd as mm
+    p = W.make_problem("wdm36", T=2 ** 10, n_steps=1)
+    plan = mm.kerr_plan(p.S, precision)
+    Sp = packed(p.S)
+    check(plan, Sp)
+    e = plan["entries"]
+    # the 70 % masked tensor leaves well under the dense block count multiplied
+    assert e["nonzero"] / e["dense"] < 0.35
+    assert e["multiplied"] / e["dense"] < (0.65 if precision == 0 else 0.85)
+
+
+def test_planted_dropped_block_is_caught():
+    import paper_1901_01895_amd as mm
+    p = W.make_problem("wdm36", T=2 ** 10, n_steps=1)
+    plan = mm.kerr_plan(p.S, 0)
+    Sp = packed(p.S)
+    # mistake: remove the first listed k-step of the first non-empty pass
+    i = next(j for j, ps in enumerate(plan["passes"]) if ps[3] > 0)
+    rt0, nt, off, n = plan["passes"][i]
+    klist = np.delete(plan["klist"], off)
+    passes = plan["passes"].copy()
+    passes[i, 3] -= 1
+    passes[i + 1:, 2] -= 1
+    assert uncovered(dict(plan, passes=passes, klist=klist), Sp) > 0
+
+
+def test_sparse_random_pattern_covered():
+    """A symmetric tensor with random whole-class zeros (not by mode group)."""
+    import paper_1901_01895_amd as mm
+    rng = np.random.default_rng(43)
+    M = 12
+    S = W.symmetric_gaussian_tensor(M, rng)
+    keep = rng.random((M,) * 4) < 0.4
+    keep = keep | keep.transpose(0, 2, 1, 3)
+    keep = keep & keep.transpose(3, 1, 2, 0)   # zero set symmetric in (l,m) and (p,n)
+    S = np.where(keep, S, 0.0).astype(np.float32)
+    for precision in (0, 1):
+        plan = mm.kerr_plan(S, precision)
+        check(plan, packed(S))
+
+
+def test_plan_rejects_bad_arguments():
+    import paper_1901_01895_amd as mm
+    with pytest.raises(mm.MMNLSEError):
+        mm.kerr_plan(np.ones((1, 1, 1, 1), np.float32), precision=5)
