@@ -24,6 +24,7 @@ from .rk4ip import (  # noqa: F401
     propagate_steps,
     StepControlError,
     rk4ip_step,
+    ssfm_agrawal_step,
     ssfm_rk4_step,
     step_doubling_estimate,
     time_grid,

@@ -39,6 +39,9 @@ Pins (tests/test_oracle_pins.py, all CPU):
   dispersion, and equality with the tensor form S_plmn = kappa_pm d_lp d_mn;
 * SSFM-RK4 (Eq. 4): exact for the linear part, identical to RK4IP without
   dispersion, second order on the soliton;
+* SSFM-Agrawal (Eq. 4, iterated trapezoidal nonlinear step, Manakov form):
+  exact for the linear part, exact without dispersion for any h, second
+  order on the soliton (first order with a single pass);
 * adaptive step size (step doubling): exact and doubling steps for the
   linear part, accepted steps scaling as tol^(-1/5) (fifth-order local
   error, Section 3.2), global error below the summed local tolerances,
@@ -56,7 +59,7 @@ import numpy as np
 __all__ = [
     "time_grid", "angular_frequencies", "linear_operator", "half_step_propagator",
     "apply_linear", "KerrGeneric", "KerrPacked", "KerrManakov", "kerr_term", "rk4ip_step",
-    "propagate", "power", "step_doubling_estimate", "ssfm_rk4_step", "propagate_adaptive",
+    "propagate", "power", "step_doubling_estimate", "ssfm_rk4_step", "ssfm_agrawal_step", "propagate_adaptive",
     "propagate_steps", "StepControlError",
 ]
 
@@ -230,6 +233,25 @@ def ssfm_rk4_step(A: np.ndarray, E: np.ndarray, h: float, N) -> np.ndarray:
     return apply_linear(X, E)
 
 
+def ssfm_agrawal_step(A: np.ndarray, E: np.ndarray, h: float, N, iterations: int = 2) -> np.ndarray:
+    """Symmetric split-step of Eq. (4) with the nonlinear integral taken by the
+    iterated trapezoidal rule (the paper's "SSFM-Agrawal", after Agrawal's
+    Nonlinear Fiber Optics), for the Manakov/XPM operator of Eq. (1).  That
+    operator multiplies each mode by i gamma Phi_a, Phi = kappa |A|^2, so its
+    exponential is a phase rotation: exp(int N dz) A_a = exp(i gamma int Phi_a dz) A_a.
+    int_z^{z+h} Phi dz ~ h/2 (Phi(z) + Phi(z+h)); Phi(z+h) is first taken equal
+    to Phi(z), then recomputed from the field reached at z+h, `iterations`
+    passes in all.  N must be a KerrManakov.  Global error O(h^2)."""
+    kappa, gamma = N.kappa, N.gamma
+    phi_z = kappa @ (np.abs(A) ** 2)
+    Ah = apply_linear(A, E)
+    phi_end = phi_z
+    for _ in range(iterations):
+        out = apply_linear(Ah * np.exp(0.5j * gamma * h * (phi_z + phi_end)), E)
+        phi_end = kappa @ (np.abs(out) ** 2)
+    return out
+
+
 def _kerr_for(S, gamma, kerr):
     if kerr is not None and not isinstance(kerr, str):
         return kerr
@@ -244,8 +266,9 @@ def propagate(A0: np.ndarray, beta: np.ndarray, alpha: np.ndarray | None, S: np.
               callback=None, method: str = "rk4ip") -> np.ndarray:
     """n_steps fixed steps of size h from A0 (promoted to complex128).
 
-    ``method`` is "rk4ip" (Eq. 6, default) or "ssfm_rk4" (Eq. 4 with an RK4
-    nonlinear step).  ``kerr`` may be None/"generic", "packed" (S must be
+    ``method`` is "rk4ip" (Eq. 6, default), "ssfm_rk4" (Eq. 4 with an RK4
+    nonlinear step) or "ssfm_agrawal" (Eq. 4 with the iterated trapezoidal
+    nonlinear step; Manakov operator only).  ``kerr`` may be None/"generic", "packed" (S must be
     symmetric in (l,m) and (p,n)), or a ready callable.  ``callback(step, A)``
     is called after each step when given.
     """
@@ -257,6 +280,10 @@ def propagate(A0: np.ndarray, beta: np.ndarray, alpha: np.ndarray | None, S: np.
         step = rk4ip_step
     elif method == "ssfm_rk4":
         step = ssfm_rk4_step
+    elif method == "ssfm_agrawal":
+        if not isinstance(N, KerrManakov):
+            raise ValueError("ssfm_agrawal needs the Manakov operator (kerr=KerrManakov(kappa, gamma))")
+        step = ssfm_agrawal_step
     else:
         raise ValueError(method)
     for s in range(n_steps):

@@ -369,6 +369,67 @@ def test_ssfm_is_second_order_and_less_accurate_than_rk4ip():
 
 
 # ----------------------------------------------------------------------------
+# symmetric split-step with the iterated trapezoidal nonlinear step (SSFM-Agrawal)
+# ----------------------------------------------------------------------------
+
+def _agrawal_gaussian_errors(iterations, ns=(50, 100)):
+    """Relative error of SSFM-Agrawal on a reshaping Gaussian pulse (N^2 = 2)
+    against 4000 RK4IP steps (the RK4IP oracle is pinned above)."""
+    T, dt, T0, b2, g, L = 1024, 0.1, 2.0, -20.0, 1.3, 0.2
+    t = oracle.time_grid(T, dt)
+    beta = np.array([[0.0, 0.0, b2]])
+    P0 = 2.0 * abs(b2) / (g * T0 ** 2)
+    A0 = (math.sqrt(P0) * np.exp(-t ** 2 / (2 * T0 ** 2)))[None, :].astype(np.complex128)
+    N = oracle.KerrManakov(np.array([[1.0]]), g)
+    ref = oracle.propagate(A0, beta, None, None, g, dt, L / 4000, 4000, kerr=N)
+    errs = []
+    for n in ns:
+        E = oracle.half_step_propagator(oracle.angular_frequencies(T, dt), beta, None, L / n)
+        A = A0.copy()
+        for _ in range(n):
+            A = oracle.ssfm_agrawal_step(A, E, L / n, N, iterations)
+        errs.append(_rel(A, ref))
+    return errs
+
+
+def test_agrawal_linear_part_exact():
+    """gamma = 0: two half steps per step give exp(h L) exactly (GVD closed form)."""
+    T, dt, T0, b2, z = 8192, 0.05, 3.0, -20.0, 0.7
+    t = oracle.time_grid(T, dt)
+    A0 = np.exp(-t ** 2 / (2 * T0 ** 2))[None, :]
+    out = oracle.propagate(A0, np.array([[0.0, 0.0, b2]]), None, None, 0.0, dt, z / 35, 35,
+                           kerr=oracle.KerrManakov(np.array([[1.0]]), 0.0), method="ssfm_agrawal")
+    c = T0 ** 2 - 1j * b2 * z
+    assert _rel(out[0], T0 / np.sqrt(c) * np.exp(-t ** 2 / (2 * c))) < 1e-12
+
+
+def test_agrawal_exact_without_dispersion_at_any_step():
+    """beta = 0: |A_b| is invariant, so Phi = kappa |A|^2 is constant and the
+    trapezoidal phase is exact: A_a(z) = A_a(0) exp(i gamma Phi_a z), even in
+    two steps of half the length."""
+    rng = _rng(24)
+    M, T = 4, 64
+    kappa = rng.uniform(0.2, 1.0, (M, M))
+    A0 = _crandn(rng, M, T)
+    g, z = 1.3, 0.9
+    out = oracle.propagate(A0, np.zeros((M, 1)), None, None, g, 1.0, z / 2, 2,
+                           kerr=oracle.KerrManakov(kappa, g), method="ssfm_agrawal")
+    exact = A0 * np.exp(1j * g * (kappa @ np.abs(A0) ** 2) * z)
+    assert _rel(out, exact) < 1e-14
+
+
+def test_agrawal_is_second_order_and_one_pass_is_first_order():
+    """With the end-point phase recomputed (two passes) the scheme is symmetric
+    and globally O(h^2): the error on a reshaping pulse falls ~4x per step
+    halving.  A single pass evaluates the phase at the start only: O(h), ~2x."""
+    e2 = _agrawal_gaussian_errors(2)
+    assert 3.5 < e2[0] / e2[1] < 4.5
+    e1 = _agrawal_gaussian_errors(1)
+    assert 1.7 < e1[0] / e1[1] < 2.3
+    assert e1[1] > 10 * e2[1]
+
+
+# ----------------------------------------------------------------------------
 # adaptive step size from the step-doubling estimate
 # ----------------------------------------------------------------------------
 
@@ -554,3 +615,27 @@ def test_mutant_coarse_kept_fails_adaptive_error_pin(monkeypatch):
     out, tr = R.propagate_adaptive(A0, p.beta, None, p.S, p.gamma, p.dt, z0, tol, 0.01)
     n_acc = sum(1 for t in tr if t[3])
     assert _rel(out, ref) > n_acc * tol / 15.0
+
+
+def _agrawal_full_weight(A, E, h, N, iterations=2):
+    kappa, gamma = N.kappa, N.gamma
+    phi_z = kappa @ (np.abs(A) ** 2)
+    Ah = R.apply_linear(A, E)
+    phi_end = phi_z
+    for _ in range(iterations):
+        out = R.apply_linear(Ah * np.exp(1j * gamma * h * (phi_z + phi_end)), E)  # mistake: h, not h/2
+        phi_end = kappa @ (np.abs(out) ** 2)
+    return out
+
+
+def test_mutant_agrawal_trapezoid_weight_fails_exactness_pin(monkeypatch):
+    monkeypatch.setattr(R, "ssfm_agrawal_step", _agrawal_full_weight)
+    rng = _rng(24)
+    M, T = 4, 64
+    kappa = rng.uniform(0.2, 1.0, (M, M))
+    A0 = _crandn(rng, M, T)
+    g, z = 1.3, 0.9
+    out = R.propagate(A0, np.zeros((M, 1)), None, None, g, 1.0, z / 2, 2,
+                      kerr=oracle.KerrManakov(kappa, g), method="ssfm_agrawal")
+    exact = A0 * np.exp(1j * g * (kappa @ np.abs(A0) ** 2) * z)
+    assert _rel(out, exact) > 1e-3
