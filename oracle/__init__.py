@@ -10,6 +10,7 @@ listed in the header of ``oracle/rk4ip.py``.
 """
 
 from .rk4ip import (  # noqa: F401
+    amplifier_gain,
     angular_frequencies,
     apply_linear,
     half_step_propagator,

@@ -42,6 +42,9 @@ Pins (tests/test_oracle_pins.py, all CPU):
 * SSFM-Agrawal (Eq. 4, iterated trapezoidal nonlinear step, Manakov form):
   exact for the linear part, exact without dispersion for any h, second
   order on the soliton (first order with a single pass);
+* spans with loss-compensating amplifiers: lossless Gaussian GVD at the
+  span ends and exp(-alpha z/2) between them; lossy SPM converging at fourth
+  order to its closed form with the effective length (1 - e^{-alpha z})/alpha;
 * adaptive step size (step doubling): exact and doubling steps for the
   linear part, accepted steps scaling as tol^(-1/5) (fifth-order local
   error, Section 3.2), global error below the summed local tolerances,
@@ -60,7 +63,7 @@ __all__ = [
     "time_grid", "angular_frequencies", "linear_operator", "half_step_propagator",
     "apply_linear", "KerrGeneric", "KerrPacked", "KerrManakov", "kerr_term", "rk4ip_step",
     "propagate", "power", "step_doubling_estimate", "ssfm_rk4_step", "ssfm_agrawal_step", "propagate_adaptive",
-    "propagate_steps", "StepControlError",
+    "propagate_steps", "StepControlError", "amplifier_gain",
 ]
 
 
@@ -263,7 +266,7 @@ def _kerr_for(S, gamma, kerr):
 
 def propagate(A0: np.ndarray, beta: np.ndarray, alpha: np.ndarray | None, S: np.ndarray,
               gamma: float, dt: float, h: float, n_steps: int, kerr=None,
-              callback=None, method: str = "rk4ip") -> np.ndarray:
+              callback=None, method: str = "rk4ip", span_steps: int = 0) -> np.ndarray:
     """n_steps fixed steps of size h from A0 (promoted to complex128).
 
     ``method`` is "rk4ip" (Eq. 6, default), "ssfm_rk4" (Eq. 4 with an RK4
@@ -271,6 +274,9 @@ def propagate(A0: np.ndarray, beta: np.ndarray, alpha: np.ndarray | None, S: np.
     nonlinear step; Manakov operator only).  ``kerr`` may be None/"generic", "packed" (S must be
     symmetric in (l,m) and (p,n)), or a ready callable.  ``callback(step, A)``
     is called after each step when given.
+
+    ``span_steps`` = k > 0 puts an amplifier after every k steps (a span of
+    k*h km): see ``amplifier_gain``; the callback sees the amplified field.
     """
     A = np.array(A0, dtype=np.complex128, copy=True)
     M, T = A.shape
@@ -286,11 +292,25 @@ def propagate(A0: np.ndarray, beta: np.ndarray, alpha: np.ndarray | None, S: np.
         step = ssfm_agrawal_step
     else:
         raise ValueError(method)
+    if span_steps < 0:
+        raise ValueError("span_steps < 0")
+    g = amplifier_gain(alpha, M, span_steps * h) if span_steps else None
     for s in range(n_steps):
         A = step(A, E, h, N)
+        if g is not None and (s + 1) % span_steps == 0:
+            A = g[:, None] * A
         if callback is not None:
             callback(s + 1, A)
     return A
+
+
+def amplifier_gain(alpha: np.ndarray | None, M: int, span: float) -> np.ndarray:
+    """Field gain per mode of the noiseless, flat-gain amplifier placed after
+    each fiber span (Section 5: two 80 km spans, the fiber loss compensated
+    after each).  Flat in frequency; it restores the span's power loss
+    exp(-alpha_p span) of each mode, so the field gain is exp(alpha_p span / 2)."""
+    a = np.zeros(M) if alpha is None else np.asarray(alpha, dtype=np.float64)
+    return np.exp(0.5 * a * span)
 
 
 def power(A: np.ndarray, dt: float) -> float:

@@ -516,6 +516,57 @@ def test_adaptive_step_below_minimum_raises():
 
 
 # ----------------------------------------------------------------------------
+# spans with loss-compensating amplifiers (Section 5's 2 x 80 km link)
+# ----------------------------------------------------------------------------
+
+def _two_span_gaussian(span_steps=20):
+    """Two modes, beta2 only, different losses, two spans of 0.35 km."""
+    T, dt, T0, z_span = 8192, 0.05, 3.0, 0.35
+    b2 = np.array([-20.0, 12.0])
+    alpha = np.array([0.6, 0.25])
+    t = oracle.time_grid(T, dt)
+    A0 = np.vstack([np.exp(-t ** 2 / (2 * T0 ** 2))] * 2)
+    beta = np.column_stack([np.zeros(2), np.zeros(2), b2])
+    seen = {}
+    out = oracle.propagate(A0, beta, alpha, np.zeros((2,) * 4), 0.0, dt, z_span / span_steps,
+                           2 * span_steps, span_steps=span_steps,
+                           callback=lambda s, A: seen.setdefault(s, A.copy()))
+    def dispersed(z):   # textbook Gaussian GVD, no loss
+        c = T0 ** 2 - 1j * b2[:, None] * z
+        return T0 / np.sqrt(c) * np.exp(-t[None, :] ** 2 / (2 * c))
+    return out, seen, dispersed, alpha, z_span, span_steps
+
+
+def test_spans_restore_loss_and_keep_dispersion():
+    """Linear propagation over two amplified spans is lossless Gaussian GVD at
+    the span ends; between amplifiers the field carries exp(-alpha z / 2)."""
+    out, seen, dispersed, alpha, z_span, k = _two_span_gaussian()
+    assert _rel(out, dispersed(2 * z_span)) < 1e-12
+    assert _rel(seen[k], dispersed(z_span)) < 1e-12
+    mid = k + k // 2   # halfway through the second span
+    expect = np.exp(-0.5 * alpha[:, None] * (z_span / 2)) * dispersed(1.5 * z_span)
+    assert _rel(seen[mid], expect) < 1e-12
+
+
+def test_spans_lossy_spm_closed_form():
+    """Without dispersion one span of lossy SPM solves exactly as
+    A(z) = A0 exp(-alpha z/2) exp(i gamma |A0|^2 L_eff(z)), L_eff = (1 - e^{-alpha z})/alpha;
+    after the amplifier the phase keeps growing by gamma |A0|^2 L_eff(span) per span."""
+    rng = _rng(40)
+    A0 = _crandn(rng, 1, 64) * 0.9
+    g, a, span = 1.3, 0.5, 1.0
+    Leff = (1.0 - math.exp(-a * span)) / a
+    expect = A0 * np.exp(1j * g * np.abs(A0) ** 2 * 3 * Leff)
+    err = []
+    for k in (50, 100):
+        out = oracle.propagate(A0, np.zeros((1, 1)), np.array([a]), np.ones((1, 1, 1, 1)), g, 1.0,
+                               span / k, 3 * k, span_steps=k)
+        err.append(_rel(out, expect))
+    assert err[1] < 2e-6
+    assert 12.0 < err[0] / err[1] < 20.0   # fourth order towards the closed form
+
+
+# ----------------------------------------------------------------------------
 # mutants: plausible mistakes planted in a copy of the oracle must fail a pin
 # ----------------------------------------------------------------------------
 
@@ -639,3 +690,11 @@ def test_mutant_agrawal_trapezoid_weight_fails_exactness_pin(monkeypatch):
                       kerr=oracle.KerrManakov(kappa, g), method="ssfm_agrawal")
     exact = A0 * np.exp(1j * g * (kappa @ np.abs(A0) ** 2) * z)
     assert _rel(out, exact) > 1e-3
+
+
+def test_mutant_power_gain_fails_span_pin(monkeypatch):
+    """An amplifier that applies the power gain exp(alpha span) to the field."""
+    monkeypatch.setattr(R, "amplifier_gain",
+                        lambda alpha, M, span: np.exp(np.asarray(alpha, dtype=np.float64) * span))
+    out, seen, dispersed, alpha, z_span, k = _two_span_gaussian()
+    assert _rel(out, dispersed(2 * z_span)) > 1e-3
