@@ -66,8 +66,14 @@ typedef enum { MMNLSE_C64 = 0, MMNLSE_C128 = 1 } mmnlse_dtype;
  * symmetric split-step of Eq. (4) with the nonlinear part integrated over h
  * by classical RK4 (the paper's "SSFM-RK4" variant, Section 3.1): half a
  * linear step, four Kerr evaluations, half a linear step (consecutive half
- * steps inside one call are applied as one full step). */
-typedef enum { MMNLSE_RK4IP = 0, MMNLSE_SSFM_RK4 = 1 } mmnlse_method;
+ * steps inside one call are applied as one full step).  SSFM_AGRAWAL
+ * (MMNLSE_KERR_MANAKOV plans only) is the same split-step with the
+ * nonlinear integral taken by the trapezoidal rule (the paper's
+ * "SSFM-Agrawal", Section 3.1): for the Manakov operator the nonlinear step
+ * is the phase rotation exp(i gamma h/2 kappa (|A(z)|^2 + |A(z+h)|^2)), with
+ * A(z+h) first replaced by A(z) and then by the field the first pass
+ * reached (two passes; three half-step propagators per step). */
+typedef enum { MMNLSE_RK4IP = 0, MMNLSE_SSFM_RK4 = 1, MMNLSE_SSFM_AGRAWAL = 2 } mmnlse_method;
 
 /* S is symmetric in (l,m) and in (p,n): S_plmn == S_pmln == S_nlmp (checked to
  * 1e-6 relative at create).  Enables the packed contraction over the
@@ -103,6 +109,12 @@ typedef struct {
   int32_t diag_every;    /* mmnlse_propagate: FP64 diagnostics every this many steps
                             (power drift; for RK4IP also the step-doubling local-error
                             estimate), 0 = only power at the end; >= 0 */
+  double span_km;        /* fiber span between amplifiers (Section 5: two 80 km spans with
+                            the loss compensated after each), 0 = one unamplified fiber of
+                            length L.  When > 0, span/h and L/span must be integers within
+                            1e-9 relative; after every span mmnlse_propagate (and the
+                            server) multiplies mode p by exp(alpha_p span / 2), the
+                            noiseless flat-gain amplifier that restores the span's loss */
 } mmnlse_config;
 
 typedef struct {
@@ -138,6 +150,8 @@ mmnlse_status mmnlse_destroy(mmnlse_t h);
 const char *mmnlse_last_error(void);
 
 /* Propagate over the configured length, L/h RK4IP steps (Eq. 6a-f).
+ * With cfg->span_km > 0 the amplifier of mmnlse_amplify acts after every
+ * span (span/h steps), the last one included.
  * With cfg->diag_every = k > 0 the steps run in chunks of k (bit-identical to
  * one run) and after each chunk the FP64 power and, for RK4IP plans, the
  * step-doubling estimate are taken from the state (see mmnlse_stats).
@@ -162,6 +176,14 @@ mmnlse_status mmnlse_propagate(mmnlse_t h, const void *A_in, void *A_out, int32_
  * schedule.  The environment variable MMNLSE_GRAPH=0 disables this.
  * Errors: E_INVALID, E_DEVICE (launch failure). */
 mmnlse_status mmnlse_advance(mmnlse_t h, void *A, int64_t n_steps);
+
+/* The amplifier at the end of a span (Section 5): multiplies row p of the
+ * device complex64 field A[M][T] in place by exp(alpha_p span_km / 2), flat in
+ * frequency, which restores the power the span's attenuation took.  For
+ * composing mmnlse_advance calls span by span (mmnlse_advance itself never
+ * amplifies).  Asynchronous.  Errors: E_INVALID (null argument, or the plan
+ * has span_km == 0), E_DEVICE. */
+mmnlse_status mmnlse_amplify(mmnlse_t h, void *A);
 
 /* One application of the half-step linear propagator exp(h/2 L) (the
  * operator of Eq. 6a) to every row: Y = IFFT(exp(h/2 L) * FFT(X)).

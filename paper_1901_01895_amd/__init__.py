@@ -17,7 +17,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmmnlse.so")
 
 FP32, SPLIT_BF16 = 0, 1
-RK4IP, SSFM_RK4 = 0, 1
+RK4IP, SSFM_RK4, SSFM_AGRAWAL = 0, 1, 2
 C64, C128 = 0, 1
 S_SYMMETRIC, KERR_GENERIC, KERR_MANAKOV = 0x1, 0x2, 0x4
 KERR_PATHS = {0: "small", 1: "tiled", 2: "mfma", 3: "manakov"}
@@ -27,7 +27,7 @@ STATUS = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NONFINITE"
 
 SYMBOLS = (
     "mmnlse_create", "mmnlse_destroy", "mmnlse_last_error", "mmnlse_propagate", "mmnlse_advance",
-    "mmnlse_linear_half_step", "mmnlse_kerr", "mmnlse_power", "mmnlse_step_doubling",
+    "mmnlse_amplify", "mmnlse_linear_half_step", "mmnlse_kerr", "mmnlse_power", "mmnlse_step_doubling",
     "mmnlse_synchronize", "mmnlse_footprint", "mmnlse_kerr_path", "mmnlse_profile",
     "mmnlse_propagate_adaptive", "mmnlse_kerr_work", "mmnlse_kerr_plan",
     "mmnlse_server_create", "mmnlse_server_submit", "mmnlse_server_poll", "mmnlse_server_wait",
@@ -49,7 +49,7 @@ class Config(ctypes.Structure):
         ("gamma", ctypes.c_double), ("h_km", ctypes.c_double), ("L_km", ctypes.c_double),
         ("precision", ctypes.c_int32), ("flags", ctypes.c_uint32),
         ("kappa", ctypes.POINTER(ctypes.c_float)), ("method", ctypes.c_int32),
-        ("diag_every", ctypes.c_int32),
+        ("diag_every", ctypes.c_int32), ("span_km", ctypes.c_double),
     ]
 
 
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mmnlse_last_error.argtypes = []
     lib.mmnlse_propagate.argtypes = [vp, vp, vp, i32, i32, ctypes.POINTER(Stats)]
     lib.mmnlse_advance.argtypes = [vp, vp, i64]
+    lib.mmnlse_amplify.argtypes = [vp, vp]
     lib.mmnlse_linear_half_step.argtypes = [vp, vp, vp]
     lib.mmnlse_kerr.argtypes = [vp, vp, vp]
     lib.mmnlse_power.argtypes = [vp, vp, dp]
@@ -146,11 +147,12 @@ def _dptr(x) -> int:
 
 
 def make_config(M, T, dt, beta, S, gamma, h, L, alpha=None, precision=FP32, symmetric=None,
-                generic=False, kappa=None, method=RK4IP, diag_every=0):
+                generic=False, kappa=None, method=RK4IP, diag_every=0, span=0.0):
     """mmnlse_config for the arguments; returns (config, arrays it points into).
 
     With ``kappa`` ([M, M]) the paper's Manakov / XPM nonlinear operator of
-    Eq. (1) is used and S is ignored (may be None)."""
+    Eq. (1) is used and S is ignored (may be None).  ``span`` > 0 (km) puts a
+    loss-compensating amplifier after every span."""
     beta = np.ascontiguousarray(np.asarray(beta, dtype=np.float64).reshape(M, -1))
     alpha = None if alpha is None else np.ascontiguousarray(np.asarray(alpha, dtype=np.float64))
     if kappa is not None:
@@ -171,16 +173,17 @@ def make_config(M, T, dt, beta, S, gamma, h, L, alpha=None, precision=FP32, symm
     cfg.precision = int(precision)
     cfg.method = int(method)
     cfg.diag_every = int(diag_every)
+    cfg.span_km = float(span)
     cfg.flags = ((S_SYMMETRIC if symmetric else 0) | (KERR_GENERIC if generic else 0)
                  | (KERR_MANAKOV if kappa is not None else 0))
     return cfg, (beta, S, alpha, kappa)
 
 
-def problem_config(p, precision=FP32, generic=False, L=None, method=RK4IP, diag_every=0):
+def problem_config(p, precision=FP32, generic=False, L=None, method=RK4IP, diag_every=0, span=0.0):
     """mmnlse_config for a workloads.Problem."""
     return make_config(p.M, p.T, p.dt, p.beta, p.S, p.gamma, p.h, p.L if L is None else L,
                        p.alpha if np.any(p.alpha) else None, precision, p.symmetric, generic,
-                       getattr(p, "kappa", None), method, diag_every)
+                       getattr(p, "kappa", None), method, diag_every, span)
 
 
 def kerr_plan(S, precision: int = FP32) -> dict:
@@ -216,11 +219,11 @@ class Propagator:
     def __init__(self, M: int, T: int, dt: float, beta, S, gamma: float, h: float, L: float,
                  alpha=None, precision: int = FP32, symmetric: bool | None = None,
                  generic: bool = False, stream=None, kappa=None, method: int = RK4IP,
-                 diag_every: int = 0):
+                 diag_every: int = 0, span: float = 0.0):
         import torch
         lib = load()
         cfg, self._keep = make_config(M, T, dt, beta, S, gamma, h, L, alpha, precision, symmetric, generic,
-                                      kappa, method, diag_every)
+                                      kappa, method, diag_every, span)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = ctypes.c_void_p()
         _check(lib.mmnlse_create(ctypes.byref(cfg), ctypes.c_void_p(self.stream.cuda_stream),
@@ -232,11 +235,11 @@ class Propagator:
 
     @classmethod
     def from_problem(cls, p, precision: int = FP32, generic: bool = False, L: float | None = None,
-                     stream=None, method: int = RK4IP, diag_every: int = 0):
+                     stream=None, method: int = RK4IP, diag_every: int = 0, span: float = 0.0):
         return cls(p.M, p.T, p.dt, p.beta, p.S, p.gamma, p.h, p.L if L is None else L,
                    alpha=p.alpha if np.any(p.alpha) else None, precision=precision,
                    symmetric=p.symmetric, generic=generic, stream=stream,
-                   kappa=getattr(p, "kappa", None), method=method, diag_every=diag_every)
+                   kappa=getattr(p, "kappa", None), method=method, diag_every=diag_every, span=span)
 
     # ------------------------------------------------------------------
     def close(self):
@@ -286,6 +289,11 @@ class Propagator:
     def advance(self, A, n_steps: int):
         """In-place device advance by n_steps (asynchronous on the plan's stream)."""
         _check(load().mmnlse_advance(self._h, ctypes.c_void_p(_dptr(A)), int(n_steps)))
+        return A
+
+    def amplify(self, A):
+        """In-place span-end amplifier exp(alpha_p span / 2) per mode (asynchronous)."""
+        _check(load().mmnlse_amplify(self._h, ctypes.c_void_p(_dptr(A))))
         return A
 
     def linear_half_step(self, X, Y=None):

@@ -64,6 +64,7 @@ static void free_plan(Plan *pl) {
   hipFree(pl->alpha_d);
   hipFree(pl->Sg);
   hipFree(pl->kappa);
+  hipFree(pl->gain);
   hipFree(pl->Sp);
   hipFree(pl->Sph);
   hipFree(pl->Spl);
@@ -92,6 +93,10 @@ static void free_plan(Plan *pl) {
 //          and, unless last, W0 = h N(A) for the next step.
 // k2 and k3 only need the same sample of every mode, so both evaluations fit
 // one launch; so do k4 and the next step's k1.
+// passes of the iterated trapezoidal nonlinear step (SSFM-Agrawal): the first
+// takes the end-point phase at z, the second from the field it reached
+constexpr int kAgrawalPasses = 2;
+
 hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float4 *E,
                      float2 *const *work, Prof *prof, bool start, bool finish) {
   if (n_steps <= 0) return hipSuccess;
@@ -136,6 +141,36 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
     k.out1 = W1;
     return kerr(k);
   };
+  if (pl.method == MMNLSE_SSFM_AGRAWAL) {
+    // Eq. (4) with the nonlinear integral by the trapezoidal rule, the end
+    // point's phase recomputed from the field reached (kAgrawalPasses passes):
+    // W0 = D A(z); W1 = D[W0 exp(i g h Phi(A))]; A = D[W0 exp(i g h/2 (Phi(A) + Phi(W1)))]
+    auto lin1 = [&](const float2 *in, float2 *out) -> hipError_t {
+      if (prof && (e = prof->record(prof->lin, pl.stream)) != hipSuccess) return e;
+      if ((e = launch_linear(pl, E, in, out, nullptr, nullptr)) != hipSuccess) return e;
+      return prof ? prof->record(prof->lin, pl.stream) : hipSuccess;
+    };
+    auto phase = [&](const float2 *Aend, float2 *out) -> hipError_t {
+      if (prof && (e = prof->record(prof->kerr, pl.stream)) != hipSuccess) return e;
+      if ((e = launch_manakov_phase(pl, h, A, Aend, W0, out)) != hipSuccess) return e;
+      if (prof) {
+        prof->kerr_evals += 1;
+        return prof->record(prof->kerr, pl.stream);
+      }
+      return hipSuccess;
+    };
+    for (int64_t s = 0; s < n_steps; ++s) {
+      if ((e = lin1(A, W0)) != hipSuccess) return e;
+      const float2 *Aend = A;  // first pass: the end-point phase taken at z
+      for (int it = 0; it < kAgrawalPasses; ++it) {
+        float2 *out = it + 1 < kAgrawalPasses ? W1 : A;
+        if ((e = phase(Aend, out)) != hipSuccess) return e;
+        if ((e = lin1(out, out)) != hipSuccess) return e;
+        Aend = W1;
+      }
+    }
+    return hipSuccess;
+  }
   if (pl.method == MMNLSE_SSFM_RK4) {
     // Eq. (4): D_half, RK4 over h on A' = N(A), D_half; the two half steps
     // between consecutive steps are one full step exp(h L) (table E2).
@@ -303,8 +338,19 @@ mmnlse_status validate_config(const mmnlse_config &c, std::string &why) {
   const double ratio = c.L_km / c.h_km;
   if (std::fabs(ratio - std::round(ratio)) > 1e-9 * std::max(1.0, ratio)) return bad("L/h is not an integer");
   if (c.precision != MMNLSE_FP32 && c.precision != MMNLSE_SPLIT_BF16) return bad("unknown precision");
-  if (c.method != MMNLSE_RK4IP && c.method != MMNLSE_SSFM_RK4) return bad("unknown method");
+  if (c.method != MMNLSE_RK4IP && c.method != MMNLSE_SSFM_RK4 && c.method != MMNLSE_SSFM_AGRAWAL)
+    return bad("unknown method");
+  if (c.method == MMNLSE_SSFM_AGRAWAL && !(c.flags & MMNLSE_KERR_MANAKOV))
+    return bad("SSFM_AGRAWAL needs the Manakov operator (MMNLSE_KERR_MANAKOV)");
   if (c.diag_every < 0) return bad("diag_every < 0");
+  if (!(c.span_km >= 0) || !std::isfinite(c.span_km)) return bad("span must be >= 0");
+  if (c.span_km > 0) {
+    const double per = c.span_km / c.h_km, spans = c.L_km / c.span_km;
+    if (std::round(per) < 1 || std::fabs(per - std::round(per)) > 1e-9 * std::max(1.0, per))
+      return bad("span/h is not a positive integer");
+    if (std::fabs(spans - std::round(spans)) > 1e-9 * std::max(1.0, spans))
+      return bad("L/span is not an integer");
+  }
   for (int i = 0; i < M * c.n_beta; ++i)
     if (!std::isfinite(c.beta[i])) return bad("beta is not finite");
   if (c.alpha)
@@ -331,6 +377,7 @@ size_t estimate_plan_bytes(const mmnlse_config &cfg) {
   size_t b = 3 * MT * sizeof(float2) + MT * sizeof(float4) + T * sizeof(float4) + 1024 * sizeof(double2);
   if (cfg.method == MMNLSE_SSFM_RK4) b += MT * sizeof(float4);
   b += M * (size_t)std::max(0, cfg.n_beta) * sizeof(double) + (cfg.alpha ? M * sizeof(double) : 0);
+  if (cfg.span_km > 0) b += M * sizeof(float);
   if (cfg.flags & MMNLSE_KERR_MANAKOV) return b + M * M * sizeof(float);
   const bool sym = (cfg.flags & MMNLSE_S_SYMMETRIC) != 0;
   const bool mfma = cfg.precision == MMNLSE_SPLIT_BF16 ||
@@ -381,6 +428,10 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
   pl->precision = cfg->precision;
   pl->method = cfg->method;
   pl->diag_every = cfg->diag_every;
+  if (cfg->span_km > 0) {
+    pl->span = cfg->span_km;
+    pl->span_steps = (int64_t)std::round(cfg->span_km / cfg->h_km);
+  }
   pl->flags = cfg->flags;
   pl->stream = (hipStream_t)stream;
   hipGetDevice(&pl->device);
@@ -438,6 +489,12 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
     if ((e = dev_alloc(*pl, (void **)&pl->alpha_d, sizeof(double) * M)) != hipSuccess) goto nomem;
     if ((e = hipMemcpy(pl->alpha_d, cfg->alpha, sizeof(double) * M, hipMemcpyHostToDevice)) != hipSuccess)
       goto dev;
+  }
+  if (pl->span_steps > 0) {  // field gain of the span-end amplifier, FP64 then rounded once
+    std::vector<float> g(M);
+    for (int p = 0; p < M; ++p) g[p] = (float)std::exp(0.5 * (cfg->alpha ? cfg->alpha[p] : 0.0) * pl->span);
+    if ((e = dev_alloc(*pl, (void **)&pl->gain, sizeof(float) * M)) != hipSuccess) goto nomem;
+    if ((e = hipMemcpy(pl->gain, g.data(), sizeof(float) * M, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
   }
   if ((e = dev_alloc(*pl, (void **)&pl->E, sizeof(float4) * MT)) != hipSuccess) goto nomem;
   if ((e = launch_tabulate_E(*pl, pl->h, pl->E)) != hipSuccess) goto dev;
@@ -509,6 +566,16 @@ mmnlse_status mmnlse_advance(mmnlse_t h, void *A, int64_t n_steps) {
   return MMNLSE_OK;
 }
 
+mmnlse_status mmnlse_amplify(mmnlse_t h, void *A) {
+  g_err.clear();
+  if (!h || !A) return fail(MMNLSE_E_INVALID, "null argument");
+  Plan &pl = *h->pl;
+  if (pl.span_steps <= 0) return fail(MMNLSE_E_INVALID, "the plan has no spans (span_km == 0)");
+  const hipError_t e = launch_amplify(pl, (float2 *)A);
+  if (e != hipSuccess) return hipfail(e, "amplify");
+  return MMNLSE_OK;
+}
+
 mmnlse_status mmnlse_propagate(mmnlse_t h, const void *A_in, void *A_out, int32_t dtype, int32_t on_device,
                                mmnlse_stats *st) {
   g_err.clear();
@@ -548,11 +615,18 @@ mmnlse_status mmnlse_propagate(mmnlse_t h, const void *A_in, void *A_out, int32_
   double drift_max = 0, err_max = 0;
   int64_t points = 0;
   hipError_t e = hipSuccess;
-  if (pl.diag_every > 0) {
+  if (pl.diag_every > 0 || pl.span_steps > 0) {
+    // chunks end at every diagnostic point (multiples of diag_every, and the
+    // end) and every span end; the amplifier acts before the diagnostics
     for (int64_t done = 0; done < pl.n_steps && e == hipSuccess;) {
-      const int64_t c = std::min<int64_t>(pl.diag_every, pl.n_steps - done);
+      int64_t c = pl.n_steps - done;
+      if (pl.diag_every > 0) c = std::min<int64_t>(c, pl.diag_every - done % pl.diag_every);
+      if (pl.span_steps > 0) c = std::min<int64_t>(c, pl.span_steps - done % pl.span_steps);
       if ((e = advance_steps(pl, state, c)) != hipSuccess) break;
       done += c;
+      if (pl.span_steps > 0 && done % pl.span_steps == 0 && (e = launch_amplify(pl, state)) != hipSuccess)
+        break;
+      if (pl.diag_every == 0 || (done % pl.diag_every != 0 && done != pl.n_steps)) continue;
       double p = 0;
       if ((e = reduce_norms(pl, state, nullptr, MT, &p, nullptr)) != hipSuccess) break;
       drift_max = std::max(drift_max, std::fabs(p / p_in - 1.0));

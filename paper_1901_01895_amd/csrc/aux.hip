@@ -1,6 +1,7 @@
-// Field conversions and the FP64 reductions used for the power invariant
-// (total power dt*sum|A|^2 is conserved by Eq. 1 when alpha = 0 and the
-// Kerr tensor satisfies S_plmn == S_lpnm) and the step-doubling estimate.
+// Field conversions, the span-end amplifier, and the FP64 reductions used
+// for the power invariant (total power dt*sum|A|^2 is conserved by Eq. 1 when
+// alpha = 0 and the Kerr tensor satisfies S_plmn == S_lpnm) and the
+// step-doubling estimate.
 
 #include "common.h"
 
@@ -15,6 +16,15 @@ __global__ void c128_to_c64(const double2 *__restrict__ in, float2 *__restrict__
 __global__ void c64_to_c128(const float2 *__restrict__ in, double2 *__restrict__ out, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     out[i] = make_double2((double)in[i].x, (double)in[i].y);
+}
+
+// A[p][t] *= g[p]: the flat-gain amplifier after a span (row p = i >> logT)
+__global__ void amplify(float2 *__restrict__ A, const float *__restrict__ g, size_t n, int logT) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float s = g[i >> logT];
+    const float2 v = A[i];
+    A[i] = make_float2(s * v.x, s * v.y);
+  }
 }
 
 constexpr int RB = 256;
@@ -59,6 +69,13 @@ hipError_t launch_convert_c128_to_c64(const Plan &pl, const double2 *in, float2 
 
 hipError_t launch_convert_c64_to_c128(const Plan &pl, const float2 *in, double2 *out, size_t n) {
   hipLaunchKernelGGL(c64_to_c128, dim3(grid_for(n)), dim3(256), 0, pl.stream, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_amplify(const Plan &pl, float2 *A) {
+  const size_t n = (size_t)pl.M * pl.T;
+  hipLaunchKernelGGL(amplify, dim3(grid_for(n)), dim3(256), 0, pl.stream, A, (const float *)pl.gain, n,
+                     pl.logT);
   return hipGetLastError();
 }
 

@@ -88,6 +88,8 @@ struct Plan {
   int precision = MMNLSE_FP32;
   int method = MMNLSE_RK4IP;
   int diag_every = 0;  // propagate: diagnostics every this many steps (0 = end only)
+  int64_t span_steps = 0;  // steps per amplified span (0 = no amplifiers)
+  double span = 0;         // span length in km
   uint32_t flags = 0;
   KerrPath kerr_path = KERR_GENERIC;
   // FFT decomposition: single pass in LDS when !four_step, else T = N1 * N2
@@ -112,6 +114,7 @@ struct Plan {
   double Ea_h = 0;        // trial step the two tables hold (0 = none)
   float *Sg = nullptr;    // generic tensor layout [p][n][m][l]
   float *kappa = nullptr; // Manakov coupling matrix [a][b]
+  float *gain = nullptr;  // [M] span-end field gain exp(alpha_p span / 2) (span_steps > 0)
   // packed symmetric tensor (matrix-core path): rows r = (p<=n), cols q = (l<=m)
   int P = 0, Ppad = 0;
   float *Sp = nullptr;          // [Ppad][Ppad] FP32, weight 2 for l<m folded in
@@ -159,8 +162,13 @@ int mfma_tile_width(int M, int T);
 hipError_t launch_linear(const Plan &pl, const float4 *E, const float2 *in0, float2 *out0,
                          const float2 *in1, float2 *out1);
 hipError_t launch_kerr(const Plan &pl, double h, const KerrLaunch &k);
+// out = DA * exp(i (h gamma / 2) kappa (|Az|^2 + |Aend|^2)) (Manakov form, SSFM-Agrawal)
+hipError_t launch_manakov_phase(const Plan &pl, double h, const float2 *Az, const float2 *Aend,
+                                const float2 *DA, float2 *out);
 // E[p][pos] = exp(h/2 L_p)/T (hi + lo) in the FFT's storage order, from beta_d / alpha_d
 hipError_t launch_tabulate_E(const Plan &pl, double h, float4 *E);
+// A[p][:] *= gain[p] in place (the amplifier after a span; needs pl.gain)
+hipError_t launch_amplify(const Plan &pl, float2 *A);
 hipError_t launch_convert_c128_to_c64(const Plan &pl, const double2 *in, float2 *out, size_t n);
 hipError_t launch_convert_c64_to_c128(const Plan &pl, const float2 *in, double2 *out, size_t n);
 // FP64 sum of |x|^2 (and of |x - y|^2 when y != nullptr) -> host values (synchronises)

@@ -253,6 +253,36 @@ __global__ __launch_bounds__(TT * GW) void kerr_manakov(KArgs a) {
   }
 }
 
+// Nonlinear step of the split-step with the iterated trapezoidal rule for
+// the Manakov form (Eq. 4 with Eq. 1's operator): the exponential of the
+// integrated operator is a phase rotation per mode,
+//   out0 = src1 * exp(i (h gamma / 2) sum_b kappa_ab (|src0_b|^2 + |src2_b|^2)),
+// src0 = A(z), src2 = the current estimate of A(z+h), src1 = D A(z).  A
+// workgroup owns 64 samples of every mode and stages the intensities in LDS
+// before writing, so out0 may be src0 or src2.
+__global__ __launch_bounds__(TT * GW) void manakov_phase(KArgs a) {
+  extern __shared__ float shf[];
+  float *Is = shf;  // |A(z)|^2 + |A_end|^2
+  const int t0 = blockIdx.x * TT;
+  const int lane = threadIdx.x & (TT - 1);
+  const int w = threadIdx.x / TT;
+  for (int idx = threadIdx.x; idx < a.M * TT; idx += TT * GW) {
+    const size_t g = (size_t)(idx / TT) * a.T + t0 + (idx % TT);
+    const float2 u = a.src0[g], v = a.src2[g];
+    Is[idx] = fmaf(u.x, u.x, u.y * u.y) + fmaf(v.x, v.x, v.y * v.y);
+  }
+  __syncthreads();
+  for (int p0 = w; p0 < a.M; p0 += GW) {
+    const int p = __builtin_amdgcn_readfirstlane(p0);
+    const float ang = 0.5f * a.hg * xpm_phase(a, Is, p, lane);
+    float sn, cs;
+    sincosf(ang, &sn, &cs);
+    const size_t g = (size_t)p * a.T + t0 + lane;
+    const float2 x = a.src1[g];
+    a.out0[g] = make_float2(x.x * cs - x.y * sn, x.x * sn + x.y * cs);
+  }
+}
+
 hipError_t go_manakov(const KArgs &a, KerrStage st, hipStream_t s) {
   dim3 grid(a.T / TT);
   const size_t shm = (size_t)(st == STAGE_K4 ? 2 : 1) * a.M * TT * sizeof(float);
@@ -312,6 +342,27 @@ hipError_t go_tiled(const KArgs &a, KerrStage st, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k);
+
+hipError_t launch_manakov_phase(const Plan &pl, double h, const float2 *Az, const float2 *Aend,
+                                const float2 *DA, float2 *out) {
+  KArgs a{};
+  a.src0 = Az;
+  a.src1 = DA;
+  a.src2 = Aend;
+  a.out0 = out;
+  a.kappa = pl.kappa;
+  a.hg = (float)(h * pl.gamma);
+  a.M = pl.M;
+  a.T = pl.T;
+  const size_t shm = (size_t)a.M * TT * sizeof(float);
+  if (shm > 65536) {
+    const hipError_t e = hipFuncSetAttribute((const void *)manakov_phase, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(manakov_phase, dim3(a.T / TT), dim3(TT * GW), shm, pl.stream, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_kerr(const Plan &pl, double h, const KerrLaunch &k) {
   if (pl.kerr_path == KERR_MFMA) return launch_kerr_mfma(pl, h, k);

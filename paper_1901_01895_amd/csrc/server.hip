@@ -38,7 +38,7 @@ struct SReq {
   uint64_t ticket = 0;
   mmnlse_config cfg{};
   std::vector<double> beta, alpha;
-  std::vector<float> S;
+  std::vector<float> S, kappa;
   std::vector<unsigned char> in, out;
   int32_t dtype = MMNLSE_C64;
   size_t bytes = 0;
@@ -189,9 +189,16 @@ void worker_main(mmnlse_server *s) {
     // one scheduling round: every resident request advances, streams in parallel
     for (SReq *r : s->active) {
       Plan &pl = *r->plan->pl;
-      const int64_t n = std::min<int64_t>(s->steps_per_tick, r->n_steps - r->done_steps);
-      const bool first = r->done_steps == 0, last = r->done_steps + n == r->n_steps;
+      // a round stops at a span end: the amplifier acts there and the next
+      // step starts afresh, as in mmnlse_propagate
+      const int64_t d = r->done_steps, sp = pl.span_steps;
+      int64_t n = std::min<int64_t>(s->steps_per_tick, r->n_steps - d);
+      if (sp > 0) n = std::min<int64_t>(n, sp - d % sp);
+      const bool first = d == 0 || (sp > 0 && d % sp == 0);
+      const bool span_end = sp > 0 && (d + n) % sp == 0;
+      const bool last = d + n == r->n_steps || span_end;
       hipError_t e = mmnlse::run_steps(pl, pl.buf[2], n, pl.h, pl.E, pl.buf, nullptr, first, last);
+      if (e == hipSuccess && span_end) e = mmnlse::launch_amplify(pl, pl.buf[2]);
       if (e != hipSuccess) req_error(r, MMNLSE_E_DEVICE, std::string("steps: ") + hipGetErrorString(e));
       r->done_steps += n;
     }
@@ -223,10 +230,13 @@ mmnlse_status copy_config(SReq *r, const mmnlse_config *cfg) {
   const size_t M = cfg->M;
   r->beta.assign(cfg->beta, cfg->beta + M * cfg->n_beta);
   if (cfg->alpha) r->alpha.assign(cfg->alpha, cfg->alpha + M);
-  r->S.assign(cfg->S, cfg->S + M * M * M * M);
+  if (cfg->S) r->S.assign(cfg->S, cfg->S + M * M * M * M);
+  const bool manakov = (cfg->flags & MMNLSE_KERR_MANAKOV) != 0;
+  if (manakov) r->kappa.assign(cfg->kappa, cfg->kappa + M * M);
   r->cfg.beta = r->beta.empty() ? nullptr : r->beta.data();
   r->cfg.alpha = cfg->alpha ? r->alpha.data() : nullptr;
-  r->cfg.S = r->S.data();
+  r->cfg.S = cfg->S ? r->S.data() : nullptr;
+  r->cfg.kappa = manakov ? r->kappa.data() : nullptr;
   return MMNLSE_OK;
 }
 

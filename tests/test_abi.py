@@ -60,7 +60,9 @@ def test_create_rejects_bad_arguments_without_touching_the_gpu():
     h = ctypes.c_void_p()
     for bad in (dict(T=1000), dict(T=32), dict(M=0), dict(L_km=1.05), dict(h_km=0.0),
                 dict(dt_ps=-1.0), dict(precision=7), dict(n_beta=9), dict(method=5),
-                dict(diag_every=-1), dict(T=2 ** 21), dict(M=257)):
+                dict(diag_every=-1), dict(T=2 ** 21), dict(M=257), dict(method=2),
+                dict(span_km=-0.5), dict(span_km=float("nan")), dict(span_km=0.25), dict(span_km=0.3),
+                dict(span_km=0.05)):
         c = make(**bad)
         assert lib.mmnlse_create(ctypes.byref(c), None, ctypes.byref(h)) == 1, bad
         assert lib.mmnlse_last_error()

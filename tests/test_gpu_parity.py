@@ -283,6 +283,70 @@ def test_ssfm_rk4_propagation(gpu_lib, name, kw):
     P.close()
 
 
+def test_ssfm_agrawal_manakov_propagation(gpu_lib):
+    """The paper's SSFM-Agrawal variant (Eq. 4, iterated trapezoidal nonlinear
+    step) with the Manakov operator of Eq. (1), 30 rows, attenuation on."""
+    mm = gpu_lib
+    p = W.manakov_problem(M=30, T=2 ** 12, n_steps=20)
+    P = mm.Propagator.from_problem(p, method=mm.SSFM_AGRAWAL)
+    out, st = P.propagate(p.A0, stats=True)
+    ref = oracle.propagate(p.A0, p.beta, p.alpha, None, p.gamma, p.dt, p.h, p.n_steps,
+                           kerr=oracle.KerrManakov(p.kappa.astype(np.float64), p.gamma), method="ssfm_agrawal")
+    err = rel(out, ref)
+    print(f"ssfm_agrawal manakov M={p.M} T={p.T}: rel L2 = {err:.3e}", flush=True)
+    assert err < 1e-5
+    # the nonlinear step is a pure phase: power decays exactly as exp(-alpha L)
+    assert abs(st["power_out"] / st["power_in"] / np.exp(-p.alpha[0] * p.L) - 1) < 1e-5
+    P.close()
+    q = W.make_problem("qpsk6", T=2 ** 10, n_steps=1)
+    with pytest.raises(mm.MMNLSEError):       # tensor plans have no phase form
+        mm.Propagator.from_problem(q, method=mm.SSFM_AGRAWAL)
+
+
+@pytest.mark.parametrize("name", ["manakov", "qpsk6"])
+def test_amplified_spans(gpu_lib, name):
+    """Spans with the loss-compensating amplifier after each (Section 5's
+    two-span link), against the oracle; the device path span by span
+    (advance, amplify) and a run with diagnostics every 4 steps give the same
+    bits; with uniform attenuation the output power matches the oracle's."""
+    import dataclasses
+    import torch
+    mm = gpu_lib
+    if name == "manakov":
+        p = W.manakov_problem(M=30, T=2 ** 12, n_steps=40)
+        kerr = oracle.KerrManakov(p.kappa.astype(np.float64), p.gamma)
+    else:
+        p = dataclasses.replace(W.make_problem("qpsk6", T=2 ** 12, n_steps=20), alpha=np.full(6, 0.2))
+        kerr = None
+    k = 10
+    span = k * p.h
+    print(f"spans {name}: M={p.M} T={p.T} steps={p.n_steps} span={span:g} km", flush=True)
+    P = mm.Propagator.from_problem(p, span=span)
+    out, st = P.propagate(p.A0, stats=True)
+    ref = oracle.propagate(p.A0, p.beta, p.alpha, p.S, p.gamma, p.dt, p.h, p.n_steps, kerr=kerr,
+                           span_steps=k)
+    err = rel(out, ref)
+    print(f"  rel L2 = {err:.3e}, power out/in = {st['power_out'] / st['power_in']:.8f}", flush=True)
+    assert err < 1e-5
+    assert abs(st["power_out"] / oracle.power(ref, p.dt) - 1) < 1e-5
+    A = dev(p.A0)
+    for _ in range(p.n_steps // k):
+        P.advance(A, k)
+        P.amplify(A)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(A), out)
+    Q = mm.Propagator.from_problem(p, span=span, diag_every=4)
+    out_d, st_d = Q.propagate(p.A0, stats=True)
+    assert np.array_equal(out_d, out)
+    assert st_d["diag_points"] == -(-p.n_steps // 4)
+    Q.close()
+    P.close()
+    R = mm.Propagator.from_problem(p)
+    with pytest.raises(mm.MMNLSEError):       # no spans configured
+        R.amplify(dev(p.A0))
+    R.close()
+
+
 def test_propagate_periodic_diagnostics(gpu_lib):
     """diag_every = 64 on a third-order soliton over one period (256 steps): four
     diagnostic points, a result bit-identical to the undiagnosed run, and the

@@ -100,3 +100,23 @@ def test_error_paths_leave_server_usable(gpu_lib):
         out, _ = srv.wait(t)
         assert np.array_equal(out, alone(mm, p, p.L, mm.FP32))
         assert srv.counters()["failed"] == 1
+
+
+def test_spans_and_manakov_requests_served_like_alone(gpu_lib):
+    """Requests with amplified spans (rounds of 4 steps against spans of 3 and
+    5) and with the Manakov operator: bit-identical to a lone propagation."""
+    import dataclasses
+    mm = gpu_lib
+    man = W.manakov_problem(M=30, T=2 ** 12, n_steps=20)
+    q = dataclasses.replace(W.make_problem("qpsk6", T=2 ** 11, n_steps=9), alpha=np.full(6, 0.2))
+    reqs = [(man, 5 * man.h), (q, 3 * q.h), (man, 0.0)]
+    ref = []
+    for p, span in reqs:
+        P = mm.Propagator.from_problem(p, span=span)
+        ref.append(P.propagate(p.A0))
+        P.close()
+    with mm.Server(n_streams=2, steps_per_tick=4) as srv:
+        tickets = [srv.submit(p.A0, mm.problem_config(p, span=span)) for p, span in reqs]
+        outs = [srv.wait(t)[0] for t in tickets]
+    for o, r in zip(outs, ref):
+        assert np.array_equal(o, r)
