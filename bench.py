@@ -34,7 +34,17 @@ WORKLOADS = {
     "qpsk6": "qpsk6: M=6 modes, T=2^14 complex64, QPSK 32 GBd, dense symmetric S, h=100 m",
     "soliton": "soliton: M=1, T=4096, fundamental sech soliton, h=5 m",
     "wdm120": "wdm120: M=120 modes, T=2^17 complex64, 4-ch WDM QPSK, dense symmetric S, h=20 m",
+    "manakov": "manakov: M=30 rows (15 spatial modes x 2 polarizations), T=2^16 complex64, "
+               "8-ch WDM 16-QAM, Manakov/XPM operator of Eq. (1), alpha 0.23 dB/km, h=100 m",
 }
+METHODS = {"rk4ip": 0, "ssfm_rk4": 1, "ssfm_agrawal": 2}
+
+
+def manakov_flops_per_eval(M: int, T: int) -> float:
+    """Flops of one Manakov/XPM evaluation h N(X)_a = i gamma h (sum_b kappa_ab |X_b|^2) X_a:
+    |X_b|^2 (3 per mode and sample), the kappa row sums (2 M^2 per sample), and
+    the scaled rotation of X_a (3 per mode and sample)."""
+    return (2.0 * M * M + 6.0 * M) * T
 
 
 def kerr_flops_per_eval(M: int, T: int, entries: float | None = None) -> float:
@@ -59,7 +69,7 @@ def linear_bytes_per_apply(M: int, T: int, four_step: bool) -> float:
     return M * T * (16.0 * passes + 16.0)
 
 
-def cpu_baseline(p, seconds_target: float = 15.0):
+def cpu_baseline(p, seconds_target: float = 15.0, method: str = "rk4ip"):
     """Time the FP64 oracle on this host over a bounded number of steps."""
     import oracle
     try:
@@ -67,20 +77,26 @@ def cpu_baseline(p, seconds_target: float = 15.0):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
-    kern = oracle.KerrPacked(p.S, p.gamma) if p.symmetric else oracle.KerrGeneric(p.S, p.gamma)
-    E = oracle.half_step_propagator(oracle.angular_frequencies(p.T, p.dt), p.beta, None, p.h)
+    if getattr(p, "kappa", None) is not None:
+        kern = oracle.KerrManakov(p.kappa.astype(np.float64), p.gamma)
+    else:
+        kern = oracle.KerrPacked(p.S, p.gamma) if p.symmetric else oracle.KerrGeneric(p.S, p.gamma)
+    step = {"rk4ip": oracle.rk4ip_step, "ssfm_rk4": oracle.ssfm_rk4_step,
+            "ssfm_agrawal": oracle.ssfm_agrawal_step}[method]
+    alpha = p.alpha if np.any(p.alpha) else None
+    E = oracle.half_step_propagator(oracle.angular_frequencies(p.T, p.dt), p.beta, alpha, p.h)
     A = p.A0.astype(np.complex128)
     steps = 0
     t0 = time.perf_counter()
     while True:
-        A = oracle.rk4ip_step(A, E, p.h, kern)
+        A = step(A, E, p.h, kern)
         steps += 1
         el = time.perf_counter() - t0
         if el > seconds_target or steps >= p.n_steps:
             break
     v = p.M * p.T * steps / el
     return {"value": v, "unit": "mode*sample*steps/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{steps} RK4IP steps of the full {p.name} field (M={p.M}, T={p.T}), FP64 numpy, "
+            "sample": f"{steps} {method} steps of the full {p.name} field (M={p.M}, T={p.T}), FP64 numpy, "
                       f"{el:.1f} s"}
 
 
@@ -143,6 +159,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"],
                     help="precision of the headline value; the other one is reported beside it")
     ap.add_argument("--precision-only", action="store_true", help="measure only --precision")
+    ap.add_argument("--method", default="rk4ip", choices=sorted(METHODS),
+                    help="step scheme (ssfm_agrawal needs the manakov workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--requests", type=int, default=256, help="serving: number of requests")
@@ -187,7 +205,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32" else "bf16x3-split/f32-acc", "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "M": p.M, "T": p.T, "h_km": p.h,
-                   "precision": args.precision, "kerr_kernel": main_run["kerr_kernel"]},
+                   "precision": args.precision, "method": args.method,
+                   "kerr_kernel": main_run["kerr_kernel"]},
         "roofline": main_run["roofline"],
         "kernels": main_run["kernels"],
     }
@@ -196,7 +215,7 @@ def main():
             out[q] = {k: r[k] for k in ("value", "ms_per_step", "roofline", "kernels")}
             out[q]["speedup_vs_" + args.precision] = r["value"] / main_run["value"]
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds, args.method)
     print(json.dumps(out), flush=True)
 
 
@@ -268,7 +287,7 @@ def traffic_for(kernel: str, workload: str):
 def measure(mm, W, p, precision: str, args) -> dict:
     import torch
     prec = mm.FP32 if precision == "fp32" else mm.SPLIT_BF16
-    P = mm.Propagator.from_problem(p, precision=prec)
+    P = mm.Propagator.from_problem(p, precision=prec, method=METHODS[args.method])
     A0 = torch.from_numpy(p.A0.astype(np.complex64)).cuda()
     A = A0.clone()
 
@@ -294,14 +313,31 @@ def measure(mm, W, p, precision: str, args) -> dict:
     path = P.kerr_path
     work = P.kerr_work() if path == "mfma" else None
     # algorithmic: nonzero tensor entries only; executed: the blocks the kernel multiplies
-    kflops = kerr_flops_per_eval(p.M, p.T, work["nonzero"] if work else None)
-    xflops = kerr_flops_per_eval(p.M, p.T, work["multiplied"] if work else None)
+    if path == "manakov":
+        kflops = xflops = manakov_flops_per_eval(p.M, p.T)
+    else:
+        kflops = kerr_flops_per_eval(p.M, p.T, work["nonzero"] if work else None)
+        xflops = kerr_flops_per_eval(p.M, p.T, work["multiplied"] if work else None)
     evals_per_launch = prof["kerr_evals"] / max(prof["kerr_launches"], 1)
     kerr_tflops = kflops * evals_per_launch / (kerr_avg_ms * 1e-3) / 1e12
     exec_tflops = xflops * evals_per_launch / (kerr_avg_ms * 1e-3) / 1e12
-    lin_gbs = 2 * linear_bytes_per_apply(p.M, p.T, four) / (lin_avg_ms * 1e-3) / 1e9
+    # RK4IP's linear launches carry two fields (A and k1, then the two stage sums);
+    # the split-step schemes transform one field per launch
+    fields = 2 if args.method == "rk4ip" else 1
+    lin_gbs = fields * linear_bytes_per_apply(p.M, p.T, four) / (lin_avg_ms * 1e-3) / 1e9
     kerr_dominant = prof["kerr_ms"] >= prof["linear_ms"]
-    if kerr_dominant:
+    if kerr_dominant and path == "manakov":
+        # pointwise in t with O(M) work per sample: bound by the field passes
+        # (per step RK4IP K2, K3, K4 read + write 3 + 5 + 4 fields, SSFM-RK4
+        # adds the plain k1 launch (2) and its K4 writes one field (3), the
+        # Agrawal phase launches read 3 and write 1)
+        passes = {"rk4ip": 12, "ssfm_rk4": 13, "ssfm_agrawal": 8}[args.method]
+        kname = f"kerr_manakov_{precision}"
+        kgbs = passes * p.M * p.T * 8.0 / (prof["kerr_ms"] / args.steps * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": kgbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": kgbs / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
+                "avg_launch_ms": kerr_avg_ms, "field_passes_per_step": passes}
+    elif kerr_dominant:
         if path == "mfma" and prec == mm.SPLIT_BF16:
             bound, peak = "mfma", BF16_PEAK_TFLOPS
         elif path == "mfma":

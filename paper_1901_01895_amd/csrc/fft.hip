@@ -18,6 +18,10 @@
 //           transposed bin order), inverse FFT over k2
 //   pass C: times W_T^(-n2*k1), inverse FFT over k1 per column
 // All passes work in place, each workgroup owning disjoint elements.
+// The twiddles of an L-point transform in the four-step passes are the
+// entries W_L^j = W_T^(j T/L) of the table; a workgroup copies those L
+// entries to LDS first (at most 16 KB) so that its butterflies read them
+// there instead of through the vector memory path.
 
 #include "common.h"
 
@@ -110,6 +114,14 @@ __device__ __forceinline__ void lds_fft(float2 *buf, const float4 *__restrict__ 
   if (LOG & 1) stockham_stage<2, L, NB, ES, BS, NT, INV>(buf, Ns, logT - (logNs + 1), tw);
 }
 
+// twl[j] = tw[j << (logT - logL)] = W_L^j for j < L, copied to LDS; the
+// stages index it with logL in place of logT and read the same values
+template <int L, int NT>
+__device__ __forceinline__ void load_twiddles(float4 *twl, const float4 *__restrict__ tw, int logT) {
+  constexpr int LOG = ilog2c(L);
+  for (int j = threadIdx.x; j < L; j += NT) twl[j] = tw[(size_t)j << (logT - LOG)];
+}
+
 struct LinArgs {
   const float2 *in[2];
   float2 *out[2];
@@ -156,6 +168,8 @@ constexpr int COLS = 16;  // columns per workgroup in the strided passes
 template <int N1, int NT, bool INV>
 __global__ __launch_bounds__(NT) void linear_cols(LinArgs a) {
   __shared__ float2 buf[N1 * COLS];
+  __shared__ float4 twl[N1];
+  load_twiddles<N1, NT>(twl, a.tw, a.logT);
   const int job = blockIdx.y;
   const int cblocks = a.N2 / COLS;
   const int row = blockIdx.x / cblocks;
@@ -170,7 +184,7 @@ __global__ __launch_bounds__(NT) void linear_cols(LinArgs a) {
     buf[idx] = x;
   }
   __syncthreads();
-  lds_fft<N1, COLS, COLS, 1, NT, INV>(buf, a.tw, a.logT);
+  lds_fft<N1, COLS, COLS, 1, NT, INV>(buf, twl, ilog2c(N1));
   for (int idx = threadIdx.x; idx < N1 * COLS; idx += NT) {
     const int k1 = idx / COLS, c = idx % COLS;
     float2 x = buf[idx];
@@ -183,6 +197,8 @@ __global__ __launch_bounds__(NT) void linear_cols(LinArgs a) {
 template <int N2, int NB, int NT>
 __global__ __launch_bounds__(NT) void linear_rows(LinArgs a) {
   __shared__ float2 buf[N2 * NB];
+  __shared__ float4 twl[N2];
+  load_twiddles<N2, NT>(twl, a.tw, a.logT);
   const int job = blockIdx.y;
   float2 *__restrict__ io = a.out[job];
   const int rows_per_mode = a.N1 / NB;
@@ -190,10 +206,10 @@ __global__ __launch_bounds__(NT) void linear_rows(LinArgs a) {
   const size_t base = (size_t)mode * a.T + (size_t)(blockIdx.x % rows_per_mode) * NB * N2;
   for (int idx = threadIdx.x; idx < N2 * NB; idx += NT) buf[idx] = io[base + idx];
   __syncthreads();
-  lds_fft<N2, NB, 1, N2, NT, false>(buf, a.tw, a.logT);
+  lds_fft<N2, NB, 1, N2, NT, false>(buf, twl, ilog2c(N2));
   for (int idx = threadIdx.x; idx < N2 * NB; idx += NT) buf[idx] = cmul_hilo(buf[idx], a.E[base + idx]);
   __syncthreads();
-  lds_fft<N2, NB, 1, N2, NT, true>(buf, a.tw, a.logT);
+  lds_fft<N2, NB, 1, N2, NT, true>(buf, twl, ilog2c(N2));
   for (int idx = threadIdx.x; idx < N2 * NB; idx += NT) io[base + idx] = buf[idx];
 }
 

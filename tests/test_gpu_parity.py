@@ -347,6 +347,36 @@ def test_amplified_spans(gpu_lib, name):
     R.close()
 
 
+def test_method_accuracy_per_step(gpu_lib):
+    """RK4IP against the two split-step variants of Section 3.1 on the Manakov
+    model (30 rows, launch amplitude x6, 2 km), errors against an FP64 RK4IP
+    run of 320 steps: at 20, 40 and 80 steps RK4IP is the most accurate and
+    SSFM-Agrawal the least, and halving h from 40 to 80 steps divides the
+    errors as fourth order (RK4IP; ratio 38 measured) and second order
+    (the split steps; 7.7 and 4.1) predict."""
+    mm = gpu_lib
+    p = W.manakov_problem(M=30, T=2 ** 12, n_steps=20)
+    A0 = (p.A0.astype(np.complex128) * 6.0).astype(np.complex64)
+    L = 2.0
+    kerr = oracle.KerrManakov(p.kappa.astype(np.float64), p.gamma)
+    ref = oracle.propagate(A0, p.beta, p.alpha, None, p.gamma, p.dt, L / 320, 320, kerr=kerr)
+    err = {}
+    for name, m in (("rk4ip", mm.RK4IP), ("ssfm_rk4", mm.SSFM_RK4), ("ssfm_agrawal", mm.SSFM_AGRAWAL)):
+        err[name] = []
+        for n in (20, 40, 80):
+            P = mm.Propagator(p.M, p.T, p.dt, p.beta, None, p.gamma, L / n, L, alpha=p.alpha,
+                              kappa=p.kappa, method=m)
+            err[name].append(rel(P.propagate(A0), ref))
+            P.close()
+        print(f"{name:13s} " + " ".join(f"{e:.3e}" for e in err[name]), flush=True)
+    for i in range(3):
+        assert err["rk4ip"][i] < err["ssfm_rk4"][i] < err["ssfm_agrawal"][i]
+    ratio = {k: v[1] / v[2] for k, v in err.items()}
+    assert ratio["rk4ip"] > 16
+    assert 3 < ratio["ssfm_rk4"] < 12
+    assert 3 < ratio["ssfm_agrawal"] < 6
+
+
 def test_propagate_periodic_diagnostics(gpu_lib):
     """diag_every = 64 on a third-order soliton over one period (256 steps): four
     diagnostic points, a result bit-identical to the undiagnosed run, and the

@@ -294,6 +294,8 @@ def make_problem(name: str, T: int | None = None, n_steps: int | None = None,
         if n_steps is not None:
             kw["n_steps"] = n_steps
         return soliton_problem(**kw)
+    if name == "manakov":
+        return manakov_problem(M=M or 30, T=T or 2 ** 16, n_steps=n_steps or 100)
     if name == "qpsk6":
         cfg, M = 1, (M or 6)
         T = T or 2 ** 14
