@@ -131,6 +131,11 @@ typedef struct {
 
 typedef struct mmnlse_ctx *mmnlse_t;
 
+/* Device fields.  Every device pointer to a complex64 field [M][T] passed to
+ * the calls below must be 16-byte aligned (hipMalloc and torch allocations
+ * are): the transforms move two samples per access.  A misaligned pointer is
+ * E_INVALID. */
+
 /* Create a propagation plan on the current HIP device.
  * Copies beta, alpha and S to the device, tabulates exp(h/2 L) per mode and
  * bin in FP64 on the device (stored as FP32 hi + lo), the FFT twiddles

@@ -47,6 +47,10 @@ static inline float4 split_hilo(double re, double im) {
 // Tabulate E_p(f) = exp(h/2 * L_p(w_f)) / T in the FFT's storage order;
 // L_p(w) = -alpha_p/2 + i sum_n beta_{n,p} (-w)^n / n! (Eq. 1 in the
 // frequency domain with the exp(-i w t) forward kernel), w_f = 2 pi fftfreq.
+// device fields are accessed two samples (16 bytes) at a time
+static bool misaligned(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15) != 0; }
+static const char *kAlign = "device field pointers must be 16-byte aligned";
+
 static hipError_t dev_alloc(Plan &pl, void **p, size_t bytes) {
   hipError_t e = hipMalloc(p, bytes);
   if (e == hipSuccess) pl.bytes += bytes;
@@ -560,6 +564,7 @@ mmnlse_status mmnlse_advance(mmnlse_t h, void *A, int64_t n_steps) {
   g_err.clear();
   if (!h || !A) return fail(MMNLSE_E_INVALID, "null argument");
   if (n_steps < 0) return fail(MMNLSE_E_INVALID, "n_steps < 0");
+  if (misaligned(A)) return fail(MMNLSE_E_INVALID, kAlign);
   Plan &pl = *h->pl;
   hipError_t e = advance_steps(pl, (float2 *)A, n_steps);
   if (e != hipSuccess) return hipfail(e, "advance");
@@ -581,6 +586,7 @@ mmnlse_status mmnlse_propagate(mmnlse_t h, const void *A_in, void *A_out, int32_
   g_err.clear();
   if (!h || !A_in || !A_out) return fail(MMNLSE_E_INVALID, "null argument");
   if (dtype != MMNLSE_C64 && dtype != MMNLSE_C128) return fail(MMNLSE_E_INVALID, "unknown dtype");
+  if (on_device && (misaligned(A_in) || misaligned(A_out))) return fail(MMNLSE_E_INVALID, kAlign);
   Plan &pl = *h->pl;
   const size_t MT = (size_t)pl.M * pl.T;
   float2 *state = pl.buf[2];
@@ -673,6 +679,7 @@ mmnlse_status mmnlse_propagate(mmnlse_t h, const void *A_in, void *A_out, int32_
 mmnlse_status mmnlse_linear_half_step(mmnlse_t h, const void *X, void *Y) {
   g_err.clear();
   if (!h || !X || !Y) return fail(MMNLSE_E_INVALID, "null argument");
+  if (misaligned(X) || misaligned(Y)) return fail(MMNLSE_E_INVALID, kAlign);
   Plan &pl = *h->pl;
   hipError_t e = launch_linear(pl, pl.E, (const float2 *)X, (float2 *)Y, nullptr, nullptr);
   if (e != hipSuccess) return hipfail(e, "linear");
@@ -735,6 +742,7 @@ static mmnlse_status step_doubling_delta(Plan &pl, const void *X, double *delta)
 mmnlse_status mmnlse_step_doubling(mmnlse_t h, const void *X, double *delta) {
   g_err.clear();
   if (!h || !X || !delta) return fail(MMNLSE_E_INVALID, "null argument");
+  if (misaligned(X)) return fail(MMNLSE_E_INVALID, kAlign);
   return step_doubling_delta(*h->pl, X, delta);
 }
 
@@ -756,6 +764,7 @@ mmnlse_status mmnlse_propagate_adaptive(mmnlse_t h, void *A, const mmnlse_adapti
   g_err.clear();
   if (!h || !A || !ac || !res) return fail(MMNLSE_E_INVALID, "null argument");
   if (log_cap < 0 || (log_cap > 0 && !log)) return fail(MMNLSE_E_INVALID, "log_cap > 0 needs a log array");
+  if (misaligned(A)) return fail(MMNLSE_E_INVALID, kAlign);
   Plan &pl = *h->pl;
   if (pl.method != MMNLSE_RK4IP) return fail(MMNLSE_E_UNSUPPORTED, "adaptive stepping is implemented for RK4IP plans");
   const double L = ac->length_km, tol = ac->tol, hmin = ac->h_min_km;
@@ -830,6 +839,7 @@ mmnlse_status mmnlse_profile(mmnlse_t h, void *A, int64_t n_steps, double *ms, i
   g_err.clear();
   if (!h || !A || !ms || !counts) return fail(MMNLSE_E_INVALID, "null argument");
   if (n_steps < 0) return fail(MMNLSE_E_INVALID, "n_steps < 0");
+  if (misaligned(A)) return fail(MMNLSE_E_INVALID, kAlign);
   Plan &pl = *h->pl;
   Prof prof;
   hipError_t e = run_steps(pl, (float2 *)A, n_steps, pl.h, pl.E, pl.buf, &prof);

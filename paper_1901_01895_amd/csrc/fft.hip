@@ -122,6 +122,11 @@ __device__ __forceinline__ void load_twiddles(float4 *twl, const float4 *__restr
   for (int j = threadIdx.x; j < L; j += NT) twl[j] = tw[(size_t)j << (logT - LOG)];
 }
 
+// two consecutive complex samples as one 16-byte access (fields are
+// 16-byte aligned, every pair starts at an even sample index)
+__device__ __forceinline__ float4 ld2(const float2 *p) { return *reinterpret_cast<const float4 *>(p); }
+__device__ __forceinline__ void st2(float2 *p, float4 v) { *reinterpret_cast<float4 *>(p) = v; }
+
 struct LinArgs {
   const float2 *in[2];
   float2 *out[2];
@@ -136,14 +141,16 @@ struct LinArgs {
 // ---------------------------------------------------------------------------
 template <int L, int NB, int NT>
 __global__ __launch_bounds__(NT) void linear_single(LinArgs a) {
-  __shared__ float2 buf[L * NB];
+  __shared__ __align__(16) float2 buf[L * NB];
   const int job = blockIdx.y;
   const float2 *__restrict__ in = a.in[job];
   float2 *__restrict__ out = a.out[job];
   const int row0 = blockIdx.x * NB;
-  for (int idx = threadIdx.x; idx < L * NB; idx += NT) {
+  // two samples (16 bytes) per access; L is even, so a pair never straddles rows
+  for (int idx = 2 * threadIdx.x; idx < L * NB; idx += 2 * NT) {
     const int row = row0 + idx / L;
-    buf[idx] = row < a.M ? in[(size_t)row * L + (idx % L)] : make_float2(0.f, 0.f);
+    const float4 v = row < a.M ? ld2(in + (size_t)row * L + (idx % L)) : make_float4(0.f, 0.f, 0.f, 0.f);
+    st2(buf + idx, v);
   }
   __syncthreads();
   lds_fft<L, NB, 1, L, NT, false>(buf, a.tw, a.logT);
@@ -153,9 +160,9 @@ __global__ __launch_bounds__(NT) void linear_single(LinArgs a) {
   }
   __syncthreads();
   lds_fft<L, NB, 1, L, NT, true>(buf, a.tw, a.logT);
-  for (int idx = threadIdx.x; idx < L * NB; idx += NT) {
+  for (int idx = 2 * threadIdx.x; idx < L * NB; idx += 2 * NT) {
     const int row = row0 + idx / L;
-    if (row < a.M) out[(size_t)row * L + (idx % L)] = buf[idx];
+    if (row < a.M) st2(out + (size_t)row * L + (idx % L), ld2(buf + idx));
   }
 }
 
@@ -167,7 +174,7 @@ constexpr int COLS = 16;  // columns per workgroup in the strided passes
 // pass A (INV=false) and pass C (INV=true): C columns of one row
 template <int N1, int NT, bool INV>
 __global__ __launch_bounds__(NT) void linear_cols(LinArgs a) {
-  __shared__ float2 buf[N1 * COLS];
+  __shared__ __align__(16) float2 buf[N1 * COLS];
   __shared__ float4 twl[N1];
   load_twiddles<N1, NT>(twl, a.tw, a.logT);
   const int job = blockIdx.y;
@@ -177,26 +184,34 @@ __global__ __launch_bounds__(NT) void linear_cols(LinArgs a) {
   const float2 *__restrict__ in = INV ? a.out[job] : a.in[job];
   float2 *__restrict__ out = a.out[job];
   const size_t rbase = (size_t)row * a.T + c0;
-  for (int idx = threadIdx.x; idx < N1 * COLS; idx += NT) {
-    const int n1 = idx / COLS, c = idx % COLS;
-    float2 x = in[rbase + (size_t)n1 * a.N2 + c];
-    if (INV) x = cmul_hilo(x, conj_hilo(a.tw[((c0 + c) * n1) & (a.T - 1)]));
-    buf[idx] = x;
+  for (int idx = 2 * threadIdx.x; idx < N1 * COLS; idx += 2 * NT) {
+    const int n1 = idx / COLS, c = idx % COLS;  // c even: columns c, c+1
+    const float4 v = ld2(in + rbase + (size_t)n1 * a.N2 + c);
+    float2 x0 = make_float2(v.x, v.y), x1 = make_float2(v.z, v.w);
+    if (INV) {
+      x0 = cmul_hilo(x0, conj_hilo(a.tw[((c0 + c) * n1) & (a.T - 1)]));
+      x1 = cmul_hilo(x1, conj_hilo(a.tw[((c0 + c + 1) * n1) & (a.T - 1)]));
+    }
+    st2(buf + idx, make_float4(x0.x, x0.y, x1.x, x1.y));
   }
   __syncthreads();
   lds_fft<N1, COLS, COLS, 1, NT, INV>(buf, twl, ilog2c(N1));
-  for (int idx = threadIdx.x; idx < N1 * COLS; idx += NT) {
+  for (int idx = 2 * threadIdx.x; idx < N1 * COLS; idx += 2 * NT) {
     const int k1 = idx / COLS, c = idx % COLS;
-    float2 x = buf[idx];
-    if (!INV) x = cmul_hilo(x, a.tw[((c0 + c) * k1) & (a.T - 1)]);
-    out[rbase + (size_t)k1 * a.N2 + c] = x;
+    const float4 v = ld2(buf + idx);
+    float2 x0 = make_float2(v.x, v.y), x1 = make_float2(v.z, v.w);
+    if (!INV) {
+      x0 = cmul_hilo(x0, a.tw[((c0 + c) * k1) & (a.T - 1)]);
+      x1 = cmul_hilo(x1, a.tw[((c0 + c + 1) * k1) & (a.T - 1)]);
+    }
+    st2(out + rbase + (size_t)k1 * a.N2 + c, make_float4(x0.x, x0.y, x1.x, x1.y));
   }
 }
 
 // pass B: NB rows k1 of length N2: FFT, times E, inverse FFT
 template <int N2, int NB, int NT>
 __global__ __launch_bounds__(NT) void linear_rows(LinArgs a) {
-  __shared__ float2 buf[N2 * NB];
+  __shared__ __align__(16) float2 buf[N2 * NB];
   __shared__ float4 twl[N2];
   load_twiddles<N2, NT>(twl, a.tw, a.logT);
   const int job = blockIdx.y;
@@ -204,13 +219,13 @@ __global__ __launch_bounds__(NT) void linear_rows(LinArgs a) {
   const int rows_per_mode = a.N1 / NB;
   const int mode = blockIdx.x / rows_per_mode;
   const size_t base = (size_t)mode * a.T + (size_t)(blockIdx.x % rows_per_mode) * NB * N2;
-  for (int idx = threadIdx.x; idx < N2 * NB; idx += NT) buf[idx] = io[base + idx];
+  for (int idx = 2 * threadIdx.x; idx < N2 * NB; idx += 2 * NT) st2(buf + idx, ld2(io + base + idx));
   __syncthreads();
   lds_fft<N2, NB, 1, N2, NT, false>(buf, twl, ilog2c(N2));
   for (int idx = threadIdx.x; idx < N2 * NB; idx += NT) buf[idx] = cmul_hilo(buf[idx], a.E[base + idx]);
   __syncthreads();
   lds_fft<N2, NB, 1, N2, NT, true>(buf, twl, ilog2c(N2));
-  for (int idx = threadIdx.x; idx < N2 * NB; idx += NT) io[base + idx] = buf[idx];
+  for (int idx = 2 * threadIdx.x; idx < N2 * NB; idx += 2 * NT) st2(io + base + idx, ld2(buf + idx));
 }
 
 template <int L, int NB, int NT>
@@ -293,6 +308,8 @@ hipError_t launch_linear(const Plan &pl, const float4 *E, const float2 *in0, flo
   a.N1 = pl.N1;
   a.N2 = pl.N2;
   const int njobs = in1 ? 2 : 1;
+  for (const void *p : {(const void *)in0, (const void *)out0, (const void *)in1, (const void *)out1})
+    if (reinterpret_cast<uintptr_t>(p) & 15) return hipErrorInvalidValue;  // entry points check first
   if (!pl.four_step) return single_dispatch(a, njobs, pl.stream);
   hipError_t e = cols_dispatch(a, njobs, pl.stream, false);
   if (e != hipSuccess) return e;

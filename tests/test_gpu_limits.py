@@ -145,3 +145,25 @@ def test_kerr_work_counts(gpu_lib, name, kw):
     assert work["nonzero"] == nnz
     assert nnz <= work["multiplied"] <= ((len(pairs) + 31) // 32 * 32) ** 2
     P.close()
+
+
+def test_misaligned_device_field_is_rejected(gpu_lib):
+    """The transforms move two samples per 16-byte access: a field pointer
+    that is only 8-byte aligned is refused before any launch, and the plan
+    keeps working with an aligned one."""
+    mm = gpu_lib
+    import torch
+    p = W.make_problem("qpsk6", T=2 ** 10, n_steps=2)
+    P = mm.Propagator.from_problem(p)
+    flat = torch.zeros(p.M * p.T + 1, dtype=torch.complex64, device="cuda")
+    A_bad = flat[1:]
+    assert A_bad.data_ptr() % 16 == 8
+    for call in (lambda: P.advance(A_bad, 1), lambda: P.linear_half_step(A_bad)):
+        with pytest.raises(mm.MMNLSEError) as e:
+            call()
+        assert e.value.status == 1
+    A = torch.from_numpy(p.A0).cuda()
+    P.advance(A, p.n_steps)
+    torch.cuda.synchronize()
+    assert np.array_equal(A.cpu().numpy(), P.propagate(p.A0))
+    P.close()
