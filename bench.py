@@ -328,10 +328,10 @@ def measure(mm, W, p, precision: str, args) -> dict:
     kerr_dominant = prof["kerr_ms"] >= prof["linear_ms"]
     if kerr_dominant and path == "manakov":
         # pointwise in t with O(M) work per sample: bound by the field passes
-        # (per step RK4IP K2, K3, K4 read + write 3 + 5 + 4 fields, SSFM-RK4
-        # adds the plain k1 launch (2) and its K4 writes one field (3), the
-        # Agrawal phase launches read 3 and write 1)
-        passes = {"rk4ip": 12, "ssfm_rk4": 13, "ssfm_agrawal": 8}[args.method]
+        # (per step RK4IP's fused K2+K3 and K4 launches read + write 4 fields
+        # each, SSFM-RK4 adds the plain k1 launch (2) and its K4 writes one
+        # field (3), the Agrawal phase launches read 3 and write 1)
+        passes = {"rk4ip": 8, "ssfm_rk4": 9, "ssfm_agrawal": 8}[args.method]
         kname = f"kerr_manakov_{precision}"
         kgbs = passes * p.M * p.T * 8.0 / (prof["kerr_ms"] / args.steps * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": kgbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -70,7 +70,7 @@ enum KerrStage : int32_t {
 };
 
 // Kerr paths whose kernels implement STAGE_K23
-inline bool kerr_fuses_k23(KerrPath p) { return p == KERR_MFMA || p == KERR_SMALL; }
+inline bool kerr_fuses_k23(KerrPath p) { return p == KERR_MFMA || p == KERR_SMALL || p == KERR_MANAKOV; }
 
 struct KerrLaunch {
   KerrStage stage;

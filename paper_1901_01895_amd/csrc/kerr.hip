@@ -212,15 +212,47 @@ template <int STAGE>
 __global__ __launch_bounds__(TT * GW) void kerr_manakov(KArgs a) {
   extern __shared__ float shf[];
   float *Is = shf;                // |X_b|^2 of the stage argument
-  float *Is2 = shf + a.M * TT;    // |A(z+h)|^2 for the k1 of the next step (K4 only)
+  float *Is2 = shf + a.M * TT;    // K4: |A(z+h)|^2 for the next step's k1; K23: |A_I + k2/2|^2
   const int t0 = blockIdx.x * TT;
   const int lane = threadIdx.x & (TT - 1);
   const int w = threadIdx.x / TT;
   for (int idx = threadIdx.x; idx < a.M * TT; idx += TT * GW) {
-    const float2 v = stage_arg<STAGE>(a, (size_t)(idx / TT) * a.T + t0 + (idx % TT));
+    const float2 v = stage_arg<STAGE == STAGE_K23 ? STAGE_K2 : STAGE>(a, (size_t)(idx / TT) * a.T + t0 + (idx % TT));
     Is[idx] = fmaf(v.x, v.x, v.y * v.y);
   }
   __syncthreads();
+  if (STAGE == STAGE_K23) {
+    // k2 = h N(A_I + k1/2) for every mode of the tile (kept in out1), then
+    // k3 = h N(A_I + k2/2) from the intensities of that second argument;
+    // the same arithmetic as a K2 launch followed by a K3 launch.  out0 is
+    // src1 (k1): each element's k1 is read before its out0 is written, and
+    // the staging above read every mode's k1 before the barrier.
+    for (int p0 = w; p0 < a.M; p0 += GW) {
+      const int p = __builtin_amdgcn_readfirstlane(p0);
+      const float hphi = a.hg * xpm_phase(a, Is, p, lane);
+      const size_t g = (size_t)p * a.T + t0 + lane;
+      const float2 ai = a.src0[g];
+      const float2 x = caxpy(ai, 0.5f, a.src1[g]);
+      const float2 k2 = make_float2(-hphi * x.y, hphi * x.x);
+      a.out1[g] = k2;
+      const float2 x3 = caxpy(ai, 0.5f, k2);
+      Is2[p * TT + lane] = fmaf(x3.x, x3.x, x3.y * x3.y);
+    }
+    __syncthreads();
+    for (int p0 = w; p0 < a.M; p0 += GW) {
+      const int p = __builtin_amdgcn_readfirstlane(p0);
+      const float hphi = a.hg * xpm_phase(a, Is2, p, lane);
+      const size_t g = (size_t)p * a.T + t0 + lane;
+      const float2 ai = a.src0[g], k1 = a.src1[g], k2 = a.out1[g];  // k2: this thread's own write
+      const float2 x3 = caxpy(ai, 0.5f, k2);
+      const float2 k3 = make_float2(-hphi * x3.y, hphi * x3.x);
+      a.out0[g] = cadd(ai, k3);
+      float2 z = caxpy(ai, 1.f / 6.f, k1);
+      z = caxpy(z, 1.f / 3.f, k2);
+      a.out1[g] = caxpy(z, 1.f / 3.f, k3);
+    }
+    return;
+  }
   for (int p0 = w; p0 < a.M; p0 += GW) {
     const int p = __builtin_amdgcn_readfirstlane(p0);
     const float hphi = a.hg * xpm_phase(a, Is, p, lane);
@@ -285,7 +317,7 @@ __global__ __launch_bounds__(TT * GW) void manakov_phase(KArgs a) {
 
 hipError_t go_manakov(const KArgs &a, KerrStage st, hipStream_t s) {
   dim3 grid(a.T / TT);
-  const size_t shm = (size_t)(st == STAGE_K4 ? 2 : 1) * a.M * TT * sizeof(float);
+  const size_t shm = (size_t)(st == STAGE_K4 || st == STAGE_K23 ? 2 : 1) * a.M * TT * sizeof(float);
   auto launch = [&](auto kern) -> hipError_t {
     if (shm > 65536) {
       hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
@@ -299,6 +331,7 @@ hipError_t go_manakov(const KArgs &a, KerrStage st, hipStream_t s) {
     case STAGE_K2: return launch(kerr_manakov<STAGE_K2>);
     case STAGE_K3: return launch(kerr_manakov<STAGE_K3>);
     case STAGE_K4: return launch(kerr_manakov<STAGE_K4>);
+    case STAGE_K23: return launch(kerr_manakov<STAGE_K23>);
   }
   return hipErrorInvalidValue;
 }
