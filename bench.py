@@ -1,7 +1,7 @@
 """Throughput of the RK4IP step on one MI355X, with roofline and CPU baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload wdm36]
-                    [--precision fp32|split_bf16] [--no-cpu-baseline]
+                    [--precision fp32|split_bf16|split_bf16_s] [--no-cpu-baseline]
 
 A step is one RK4IP step (Eq. 6a-f of the paper: four half-step propagators,
 four Kerr evaluations, the stage combinations) over the whole field.  The
@@ -25,6 +25,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "RK4IP mode·sample·steps/s + roofline %, plain vs split-BF16; p50/p99 latency"
+PRECISIONS = ("fp32", "split_bf16", "split_bf16_s")
+DTYPES = {"fp32": "f32", "split_bf16": "bf16x3-split/f32-acc", "split_bf16_s": "bf16x2-split-S/f32-acc"}
+
+
+def precision_code(mm, name: str) -> int:
+    return {"fp32": mm.FP32, "split_bf16": mm.SPLIT_BF16, "split_bf16_s": mm.SPLIT_BF16_S}[name]
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 BF16_PEAK_TFLOPS = 2500.0
@@ -110,7 +116,7 @@ def serving(args):
 
     specs = W.serving_stream(args.requests, rate=args.rate)
     probs = [W.fiber.request_problem(sp) for sp in specs]
-    prec = mm.FP32 if args.precision == "fp32" else mm.SPLIT_BF16
+    prec = precision_code(mm, args.precision)
     cfgs = [mm.problem_config(p, precision=prec if p.M > 8 else mm.FP32) for p in probs]
     work = sum(p.M * p.T * p.n_steps for p in probs)
     lat = [None] * len(probs)
@@ -138,7 +144,7 @@ def serving(args):
         "metric": METRIC, "value": work / el, "unit": "mode*sample*steps/s", "n_gpus": 1,
         "steps": int(sum(p.n_steps for p in probs)), "warmup": 0, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if prec == mm.FP32 else "bf16x3-split/f32-acc", "data": "synthetic",
+        "dtype": DTYPES[args.precision], "data": "synthetic",
         "config": {"workload": f"serving: {len(probs)} requests, Poisson rate "
                                f"{'saturated' if args.rate is None else args.rate}/s, M in {{1,6,15,36}}, "
                                "T in {2^12,2^14,2^16}, L in {1,10,50} km",
@@ -156,8 +162,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="wdm36", choices=sorted(WORKLOADS) + ["serving"])
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "split_bf16"],
-                    help="precision of the headline value; the other one is reported beside it")
+    ap.add_argument("--precision", default="fp32", choices=list(PRECISIONS),
+                    help="precision of the headline value; the others are reported beside it")
     ap.add_argument("--precision-only", action="store_true", help="measure only --precision")
     ap.add_argument("--method", default="rk4ip", choices=sorted(METHODS),
                     help="step scheme (ssfm_agrawal needs the manakov workload)")
@@ -192,10 +198,10 @@ def main():
         return
     p = W.make_problem(args.workload)
     precs = [args.precision] if args.precision_only else \
-        [args.precision] + [q for q in ("fp32", "split_bf16") if q != args.precision]
+        [args.precision] + [q for q in PRECISIONS if q != args.precision]
     runs = {}
     for q in precs:
-        if q == "split_bf16" and not p.symmetric:
+        if q != "fp32" and not p.symmetric:
             continue
         runs[q] = measure(mm, W, p, q, args)
     main_run = runs[args.precision]
@@ -203,7 +209,7 @@ def main():
         "metric": METRIC, "value": main_run["value"], "unit": "mode*sample*steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_run["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "bf16x3-split/f32-acc", "data": "synthetic",
+        "dtype": DTYPES[args.precision], "data": "synthetic",
         "config": {"workload": WORKLOADS[args.workload], "M": p.M, "T": p.T, "h_km": p.h,
                    "precision": args.precision, "method": args.method,
                    "kerr_kernel": main_run["kerr_kernel"]},
@@ -246,8 +252,8 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, precision: str)
 
     p = W.make_problem(workload)
     copy_bytes = float(p.M * p.T * 8)
-    split = "true" if precision == "split_bf16" else "false"
-    pat = re.compile(r"kerr_mfma<\d+, \d+, " + split + ",")
+    mode = {"fp32": "0", "split_bf16": "1", "split_bf16_s": "2"}[precision]
+    pat = re.compile(r"kerr_mfma<\d+, \d+, " + mode + ",")
     fe, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
     rec = {"kernel": f"kerr_mfma_{precision}", "workload": workload, "source": "kerr_mfma.hip"}
     src = os.path.join(ROOT, "paper_1901_01895_amd", "csrc", rec["source"])
@@ -286,7 +292,7 @@ def traffic_for(kernel: str, workload: str):
 
 def measure(mm, W, p, precision: str, args) -> dict:
     import torch
-    prec = mm.FP32 if precision == "fp32" else mm.SPLIT_BF16
+    prec = precision_code(mm, precision)
     P = mm.Propagator.from_problem(p, precision=prec, method=METHODS[args.method])
     A0 = torch.from_numpy(p.A0.astype(np.complex64)).cuda()
     A = A0.clone()
@@ -338,7 +344,7 @@ def measure(mm, W, p, precision: str, args) -> dict:
                 "frac": kgbs / HBM_PEAK_GBS, "traffic": None, "kernel": kname,
                 "avg_launch_ms": kerr_avg_ms, "field_passes_per_step": passes}
     elif kerr_dominant:
-        if path == "mfma" and prec == mm.SPLIT_BF16:
+        if path == "mfma" and prec != mm.FP32:
             bound, peak = "mfma", BF16_PEAK_TFLOPS
         elif path == "mfma":
             bound, peak = "mfma", FP32_PEAK_TFLOPS

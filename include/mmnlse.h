@@ -56,8 +56,12 @@ typedef enum {
 /* Arithmetic of the Kerr contraction; FFTs and field storage are FP32 in both. */
 typedef enum {
   MMNLSE_FP32 = 0,        /* FP32 products, FP32 accumulation */
-  MMNLSE_SPLIT_BF16 = 1   /* S and A_l A_m split into bf16 hi + lo; hi*hi + hi*lo + lo*hi
+  MMNLSE_SPLIT_BF16 = 1,  /* S and A_l A_m split into bf16 hi + lo; hi*hi + hi*lo + lo*hi
                              on matrix cores with FP32 accumulation (needs a symmetric S) */
+  MMNLSE_SPLIT_BF16_S = 2 /* S split into bf16 hi + lo, A_l A_m rounded to bf16 (nearest
+                             even); hi*B + lo*B, two matrix-core products instead of three,
+                             FP32 accumulation (needs a symmetric S).  The rounding of the
+                             products dominates its error, which grows like sqrt(steps) */
 } mmnlse_precision;
 
 typedef enum { MMNLSE_C64 = 0, MMNLSE_C128 = 1 } mmnlse_dtype;

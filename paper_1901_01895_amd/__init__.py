@@ -16,7 +16,7 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libmmnlse.so")
 
-FP32, SPLIT_BF16 = 0, 1
+FP32, SPLIT_BF16, SPLIT_BF16_S = 0, 1, 2
 RK4IP, SSFM_RK4, SSFM_AGRAWAL = 0, 1, 2
 C64, C128 = 0, 1
 S_SYMMETRIC, KERR_GENERIC, KERR_MANAKOV = 0x1, 0x2, 0x4

@@ -341,7 +341,8 @@ mmnlse_status validate_config(const mmnlse_config &c, std::string &why) {
   if (!(c.L_km >= 0) || !std::isfinite(c.L_km)) return bad("L must be >= 0");
   const double ratio = c.L_km / c.h_km;
   if (std::fabs(ratio - std::round(ratio)) > 1e-9 * std::max(1.0, ratio)) return bad("L/h is not an integer");
-  if (c.precision != MMNLSE_FP32 && c.precision != MMNLSE_SPLIT_BF16) return bad("unknown precision");
+  if (c.precision != MMNLSE_FP32 && c.precision != MMNLSE_SPLIT_BF16 && c.precision != MMNLSE_SPLIT_BF16_S)
+    return bad("unknown precision");
   if (c.method != MMNLSE_RK4IP && c.method != MMNLSE_SSFM_RK4 && c.method != MMNLSE_SSFM_AGRAWAL)
     return bad("unknown method");
   if (c.method == MMNLSE_SSFM_AGRAWAL && !(c.flags & MMNLSE_KERR_MANAKOV))
@@ -369,7 +370,7 @@ mmnlse_status validate_config(const mmnlse_config &c, std::string &why) {
     why += " but MMNLSE_S_SYMMETRIC is set";
     return MMNLSE_E_INVALID;
   }
-  if (c.precision == MMNLSE_SPLIT_BF16 && !sym) return bad("split-bf16 precision needs MMNLSE_S_SYMMETRIC");
+  if (c.precision != MMNLSE_FP32 && !sym) return bad("split-bf16 precision needs MMNLSE_S_SYMMETRIC");
   return MMNLSE_OK;
 }
 
@@ -384,7 +385,7 @@ size_t estimate_plan_bytes(const mmnlse_config &cfg) {
   if (cfg.span_km > 0) b += M * sizeof(float);
   if (cfg.flags & MMNLSE_KERR_MANAKOV) return b + M * M * sizeof(float);
   const bool sym = (cfg.flags & MMNLSE_S_SYMMETRIC) != 0;
-  const bool mfma = cfg.precision == MMNLSE_SPLIT_BF16 ||
+  const bool mfma = cfg.precision != MMNLSE_FP32 ||
                     (!(cfg.flags & MMNLSE_KERR_GENERIC) && cfg.M >= 3 && sym);
   if (mfma) {
     const size_t P = M * (M + 1) / 2, Ppad = (P + 63) / 64 * 64;
@@ -455,7 +456,7 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
   const char *fpath = std::getenv("MMNLSE_KERR_PATH");
   const bool manakov = (cfg->flags & MMNLSE_KERR_MANAKOV) != 0;
   if (manakov) pl->kerr_path = KERR_MANAKOV;
-  else if (cfg->precision == MMNLSE_SPLIT_BF16) pl->kerr_path = KERR_MFMA;
+  else if (cfg->precision != MMNLSE_FP32) pl->kerr_path = KERR_MFMA;
   else if (force_generic) pl->kerr_path = KERR_GENERIC;
   else if (sym && M >= 3) pl->kerr_path = KERR_MFMA;
   else if (M <= 8) pl->kerr_path = KERR_SMALL;
@@ -884,10 +885,11 @@ mmnlse_status mmnlse_kerr_plan(const float *S, int32_t M, int32_t precision, int
   g_err.clear();
   if (!S || !counts) return fail(MMNLSE_E_INVALID, "null argument");
   if (M < 1 || M > 256) return fail(MMNLSE_E_INVALID, "M must be in 1..256");
-  if (precision != MMNLSE_FP32 && precision != MMNLSE_SPLIT_BF16) return fail(MMNLSE_E_INVALID, "unknown precision");
+  if (precision != MMNLSE_FP32 && precision != MMNLSE_SPLIT_BF16 && precision != MMNLSE_SPLIT_BF16_S)
+    return fail(MMNLSE_E_INVALID, "unknown precision");
   KerrPlan kp;
   try {
-    plan_kerr(S, M, precision == MMNLSE_SPLIT_BF16, kp);
+    plan_kerr(S, M, precision != MMNLSE_FP32, kp);
   } catch (const std::bad_alloc &) {
     return fail(MMNLSE_E_NOMEM, "host allocation");
   }

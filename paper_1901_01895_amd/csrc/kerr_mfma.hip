@@ -51,6 +51,11 @@ struct MArgs {
 typedef float floatv2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
+// Two floats to bf16 (round to nearest even), packed in element order.
+__device__ __forceinline__ uint32_t to_bf16x2(float x0, float x1) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatv2){x0, x1}, bf16x2));
+}
+
 // Two floats to bf16 hi (round to nearest even) and bf16 lo = bf16(x - hi),
 // each pair packed in one register in element order.
 __device__ __forceinline__ void split2(float x0, float x1, uint32_t &hi, uint32_t &lo) {
@@ -145,7 +150,7 @@ struct KList {
   }
 };
 
-template <int W, int RT, bool SPLIT>
+template <int W, int RT, int SPLIT>
 __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, float2 *Os, int lane, int col,
                                               int rt0, const int *kl, int len) {
   constexpr int TT = 32 * W;
@@ -242,8 +247,14 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
         for (int i = 0; i < 4; ++i) {  // elements 2i and 2i+1
           const float2 b0 = form_b(xb, o[i].x, o[i].y);
           const float2 b1 = form_b(xb, o[i].z, o[i].w);
-          split2(b0.x, b1.x, urh[i], url[i]);
-          split2(b0.y, b1.y, uih[i], uil[i]);
+          if (SPLIT == 1) {
+            split2(b0.x, b1.x, urh[i], url[i]);
+            split2(b0.y, b1.y, uih[i], uil[i]);
+          } else {  // B rounded to bf16 only
+            urh[i] = to_bf16x2(b0.x, b1.x);
+            uih[i] = to_bf16x2(b0.y, b1.y);
+            url[i] = uil[i] = 0;
+          }
         }
         const bf16x8 rh = __builtin_bit_cast(bf16x8, make_uint4(urh[0], urh[1], urh[2], urh[3]));
         const bf16x8 rl = __builtin_bit_cast(bf16x8, make_uint4(url[0], url[1], url[2], url[3]));
@@ -254,10 +265,10 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
           const bf16x8 sh = __builtin_bit_cast(bf16x8, ah[j]);
           const bf16x8 sl = __builtin_bit_cast(bf16x8, al[j]);
           cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, rh, cre[j], 0, 0, 0);
-          cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rl, cre[j], 0, 0, 0);
+          if (SPLIT == 1) cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rl, cre[j], 0, 0, 0);
           cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rh, cre[j], 0, 0, 0);
           cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, ih, cim[j], 0, 0, 0);
-          cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, il, cim[j], 0, 0, 0);
+          if (SPLIT == 1) cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, il, cim[j], 0, 0, 0);
           cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, ih, cim[j], 0, 0, 0);
         }
 #pragma unroll
@@ -289,7 +300,7 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
 // only) are dealt to the row groups, pass u to row group u % R.
 // A pass multiplies only the k-steps of its list (where its rows hold a
 // nonzero entry); a pass with an empty list contributes nothing.
-template <int W, int R, bool SPLIT, int RTM>
+template <int W, int R, int SPLIT, int RTM>
 __device__ __forceinline__ void contract(const MArgs &a, const float2 *Xs, float2 *Os, int lane, int col,
                                          int rg) {
   for (int u = rg; u < a.npass; u += R) {
@@ -306,7 +317,7 @@ __device__ __forceinline__ void contract(const MArgs &a, const float2 *Xs, float
 // samples of column group w % W and the passes of row group w / W, and
 // scatters into that row group's partial tile; the R partials are summed in
 // a fixed order, so the result does not depend on timing.
-template <int W, int R, bool SPLIT, int RTM, int STAGE>
+template <int W, int R, int SPLIT, int RTM, int STAGE>
 __global__ __launch_bounds__(64 * W * R) void kerr_mfma(MArgs a) {
   constexpr int TT = 32 * W;
   constexpr int NT = 64 * W * R;
@@ -378,7 +389,7 @@ __global__ __launch_bounds__(64 * W * R) void kerr_mfma(MArgs a) {
   }
 }
 
-template <int W, int R, bool SPLIT, int RTM>
+template <int W, int R, int SPLIT, int RTM>
 hipError_t go(const MArgs &a, KerrStage st, hipStream_t s) {
   constexpr int TT = 32 * W;
   if (a.koff_tt != TT) return hipErrorInvalidValue;  // offsets built for another tile width
@@ -407,7 +418,7 @@ hipError_t go(const MArgs &a, KerrStage st, hipStream_t s) {
 //   M <= 64: 4 column groups (128 samples), 1 row group
 //   M <= 125: 1 column group (32 samples), 4 row groups
 //   M <= 208: 1 x 2;   M <= 256: 1 x 1
-template <bool SPLIT, int RTM>
+template <int SPLIT, int RTM>
 hipError_t go_shape(const MArgs &a, KerrStage st, hipStream_t s) {
   if (mfma_tile_width(a.M, a.T) == 128) return go<4, 1, SPLIT, RTM>(a, st, s);
   if (a.M <= 125) return go<1, 4, SPLIT, RTM>(a, st, s);
@@ -415,7 +426,7 @@ hipError_t go_shape(const MArgs &a, KerrStage st, hipStream_t s) {
   return go<1, 1, SPLIT, RTM>(a, st, s);
 }
 
-template <bool SPLIT>
+template <int SPLIT>
 hipError_t go_w(const MArgs &a, KerrStage st, hipStream_t s) {
   // row tiles per pass (fixed when the pass table was built)
   if (a.rtm == 4) return go_shape<SPLIT, 4>(a, st, s);
@@ -462,8 +473,9 @@ hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k) {
   a.P = pl.P;
   a.Ppad = pl.Ppad;
   a.next = k.next;
-  if (pl.precision == MMNLSE_SPLIT_BF16) return go_w<true>(a, k.stage, pl.stream);
-  return go_w<false>(a, k.stage, pl.stream);
+  if (pl.precision == MMNLSE_SPLIT_BF16) return go_w<1>(a, k.stage, pl.stream);
+  if (pl.precision == MMNLSE_SPLIT_BF16_S) return go_w<2>(a, k.stage, pl.stream);
+  return go_w<0>(a, k.stage, pl.stream);
 }
 
 // Build the device tables of the contraction from its host plan: the pair
@@ -471,7 +483,7 @@ hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k) {
 // their k-lists.
 hipError_t setup_mfma(Plan &pl, const float *S) {
   const int M = pl.M;
-  const bool split = pl.precision == MMNLSE_SPLIT_BF16;
+  const bool split = pl.precision != MMNLSE_FP32;  // both bf16 modes share the tables
   KerrPlan kp;
   plan_kerr(S, M, split, kp);
   const int P = kp.P, Ppad = kp.Ppad, nrt = kp.nrt, nk = kp.nk;

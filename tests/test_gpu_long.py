@@ -4,7 +4,7 @@ The FP64 oracle needs hours for this run, so its fields are precomputed at a few
 step counts by tests/golden/make_golden.py (which calls only oracle/) into
 tests/golden/cache/; this test is skipped when that cache is absent.  The GPU
 run is one uninterrupted step schedule with snapshots taken between segments.
-Bars: relative L2 <= 1e-5 (FP32 path) and <= 1e-4 (split-bf16 path).
+Bars: relative L2 <= 1e-5 (FP32 path) and <= 1e-4 (both split-bf16 paths).
 """
 
 import glob
@@ -28,7 +28,7 @@ def checkpoints(name):
     return dict(sorted(out.items()))
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("split_bf16", 1e-4)])
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("split_bf16", 1e-4), ("split_bf16_s", 1e-4)])
 def test_wdm36_full_length(gpu_lib, precision, tol):
     import torch
     mm = gpu_lib
@@ -36,7 +36,8 @@ def test_wdm36_full_length(gpu_lib, precision, tol):
     if not cps:
         pytest.skip("no cached oracle fields (run tests/golden/make_golden.py wdm36 ...)")
     p = W.make_problem("wdm36")
-    P = mm.Propagator.from_problem(p, precision=mm.FP32 if precision == "fp32" else mm.SPLIT_BF16)
+    prec = {"fp32": mm.FP32, "split_bf16": mm.SPLIT_BF16, "split_bf16_s": mm.SPLIT_BF16_S}[precision]
+    P = mm.Propagator.from_problem(p, precision=prec)
     A = torch.from_numpy(p.A0).cuda()
     done, errs = 0, {}
     for s, f in cps.items():

@@ -118,6 +118,29 @@ def test_kerr_term(gpu_lib, M, sym, generic, path, monkeypatch):
 
 
 @pytest.mark.parametrize("M", [9, 36])
+def test_kerr_term_split_bf16_s(gpu_lib, M):
+    """Two-product contraction: S as bf16 hi + lo, B = X_l X_m rounded once to
+    bf16 (relative error <= 2^-9 per product).  One evaluation is ~1.7e-3
+    from the FP64 value (a CPU model of that rounding gives 1.69e-3 / 1.67e-3
+    for these inputs), and the three-product path is far closer."""
+    mm = gpu_lib
+    T = 512
+    rng = np.random.default_rng((14, M))
+    S = W.symmetric_gaussian_tensor(M, rng).astype(np.float32)
+    X = crandn(rng, M, T)
+    ref = 0.05 * oracle.kerr_term(X.astype(np.complex128), S.astype(np.float64), 1.3)
+    errs = {}
+    for prec in (mm.SPLIT_BF16, mm.SPLIT_BF16_S):
+        P, beta, _ = make(mm, M, T, S=S, gamma=1.3, h=0.05, L=0.05, precision=prec)
+        assert P.kerr_path == "mfma"
+        errs[prec] = rel(host(P.kerr(dev(X))), ref)
+        P.close()
+    print(f"M={M}: three products {errs[mm.SPLIT_BF16]:.2e}, two {errs[mm.SPLIT_BF16_S]:.2e}", flush=True)
+    assert 1e-3 < errs[mm.SPLIT_BF16_S] < 2.5e-3
+    assert errs[mm.SPLIT_BF16] < 3e-5
+
+
+@pytest.mark.parametrize("M", [9, 36])
 def test_kerr_term_split_bf16(gpu_lib, M):
     """Split-bf16 contraction: S and B = X_l X_m each carried as bf16 hi + lo, three
     products accumulated in FP32; each product keeps ~16 significant bits, so one
@@ -186,6 +209,15 @@ def test_wdm36_reduced_split_bf16(gpu_lib):
     import paper_1901_01895_amd as mm
     _propagate_parity(gpu_lib, W.make_problem("wdm36", T=2 ** 12, n_steps=20), 1e-4,
                       precision=mm.SPLIT_BF16)
+
+
+def test_wdm36_reduced_split_bf16_s(gpu_lib):
+    """Two-product mode: the bf16 rounding of B = X_l X_m leaves ~1e-5 after
+    20 steps (a CPU model of that rounding gives 7.5e-6 after 10 and 1.3e-5
+    after 30 steps), an order of magnitude under the 1e-4 bar."""
+    import paper_1901_01895_amd as mm
+    _propagate_parity(gpu_lib, W.make_problem("wdm36", T=2 ** 12, n_steps=20), 4e-5,
+                      precision=mm.SPLIT_BF16_S)
 
 
 def test_four_step_propagation(gpu_lib):
