@@ -285,8 +285,8 @@ mmnlse_status mmnlse_footprint(const mmnlse_t h, size_t *bytes);
 /* Work of one Kerr evaluation per time sample on the matrix-core path
  * (E_UNSUPPORTED for the other paths), as counts of packed tensor entries:
  * entries[0] = P*P (P = M(M+1)/2, the dense packed contraction),
- * entries[1] = entries in the blocks the kernel multiplies (32 rows by one
- * k-step, kept when they hold a nonzero entry; padding included),
+ * entries[1] = entries in the blocks the kernel multiplies (32 row slots by
+ * one k-step, kept when they hold a nonzero entry; padding included),
  * entries[2] = nonzero entries.  Each entry costs 4 flops per sample (a real
  * multiply-add on the real and on the imaginary part of B_q).  Host array
  * of 3 doubles. */
@@ -295,19 +295,21 @@ mmnlse_status mmnlse_kerr_work(const mmnlse_t h, double *entries);
 /* Host-only dry run of the matrix-core contraction plan for S (no device is
  * touched): the packed form Sp[(p,n)][(l,m)] = w S[p,l,m,n] (w = 2 for
  * l < m) of a tensor symmetric in (l,m) and in (p,n), over P = M(M+1)/2
- * pairs, with the pair order and the blocks (32 rows x one k-step of 8
- * columns FP32 / 16 split) that mmnlse_create would use.
- * counts (host, 6 ints, required): P, Ppad (P rounded up to 32), number of
- * passes, length of the k-list array, k-step width in columns, largest
- * number of row tiles per pass.  The arrays may be NULL; when given they
- * must hold: perm [P] (natural pair index, in the order l <= m row-major,
- * at each position), passes [4 * number of passes] (first row tile, row
- * tiles, offset into klist, count), klist [length] (k-steps each pass
- * multiplies; a block outside every list is entirely zero), entries [3]
- * (as mmnlse_kerr_work).  Call once with NULL arrays to get the sizes.
- * Errors: E_INVALID, E_NOMEM. */
+ * pairs, with the column order, the row tiles and the blocks (32 row slots
+ * x one k-step of 8 columns FP32 / 16 split) that mmnlse_create would use.
+ * counts (host, 7 ints, required): P, Ppad (P rounded up to 32: the padded
+ * column count), number of passes, length of the k-list array, k-step width
+ * in columns, largest number of row tiles per pass, number of row tiles.
+ * The arrays may be NULL; when given they must hold: perm [P] (natural pair
+ * index, in the order l <= m row-major, at each column position), rows
+ * [32 * row tiles] (natural pair index in each row slot, -1 for a zero
+ * padding row; every pair appears once), passes [4 * number of passes]
+ * (first row tile, row tiles, offset into klist, count), klist [length]
+ * (k-steps each pass multiplies; a block outside every list is entirely
+ * zero), entries [3] (as mmnlse_kerr_work).  Call once with NULL arrays to
+ * get the sizes.  Errors: E_INVALID, E_NOMEM. */
 mmnlse_status mmnlse_kerr_plan(const float *S, int32_t M, int32_t precision, int32_t *counts, int32_t *perm,
-                               int32_t *passes, int32_t *klist, double *entries);
+                               int32_t *rows, int32_t *passes, int32_t *klist, double *entries);
 
 /* Kernel used for the Kerr term: 0 = per-sample register kernel (M <= 8),
  * 1 = generic LDS kernel (any S), 2 = packed matrix-core contraction,

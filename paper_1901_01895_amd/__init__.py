@@ -116,7 +116,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mmnlse_kerr_path.argtypes = [vp, ctypes.POINTER(i32)]
     lib.mmnlse_kerr_work.argtypes = [vp, dp]
     ip = ctypes.POINTER(ctypes.c_int32)
-    lib.mmnlse_kerr_plan.argtypes = [ctypes.POINTER(ctypes.c_float), i32, i32, ip, ip, ip, ip, dp]
+    lib.mmnlse_kerr_plan.argtypes = [ctypes.POINTER(ctypes.c_float), i32, i32, ip, ip, ip, ip, ip, dp]
     lib.mmnlse_profile.argtypes = [vp, vp, i64, dp, ctypes.POINTER(ctypes.c_int64)]
     lib.mmnlse_propagate_adaptive.argtypes = [vp, vp, ctypes.POINTER(AdaptiveConfig), ctypes.POINTER(Trial),
                                               i64, ctypes.POINTER(AdaptiveResult)]
@@ -188,25 +188,27 @@ def problem_config(p, precision=FP32, generic=False, L=None, method=RK4IP, diag_
 
 def kerr_plan(S, precision: int = FP32) -> dict:
     """Host-only plan of the matrix-core contraction for tensor S [M,M,M,M]
-    (mmnlse_kerr_plan): pair order, passes of row tiles and their k-lists."""
+    (mmnlse_kerr_plan): column order, row tiles (slots with -1 padding),
+    passes of row tiles and their k-lists."""
     lib = load()
     S = np.ascontiguousarray(np.asarray(S, dtype=np.float32))
     M = S.shape[0]
     sp = S.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
-    counts = np.zeros(6, np.int32)
+    counts = np.zeros(7, np.int32)
     cp = counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-    _check(lib.mmnlse_kerr_plan(sp, M, int(precision), cp, None, None, None, None))
-    P, Ppad, npass, nk_list, kw, rtm = (int(x) for x in counts)
+    _check(lib.mmnlse_kerr_plan(sp, M, int(precision), cp, None, None, None, None, None))
+    P, Ppad, npass, nk_list, kw, rtm, nrt = (int(x) for x in counts)
     perm = np.zeros(P, np.int32)
+    rows = np.zeros(32 * nrt, np.int32)
     passes = np.zeros((max(npass, 1), 4), np.int32)
     klist = np.zeros(max(nk_list, 1), np.int32)
     entries = np.zeros(3, np.float64)
     ptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-    _check(lib.mmnlse_kerr_plan(sp, M, int(precision), cp, ptr(perm), ptr(passes), ptr(klist),
+    _check(lib.mmnlse_kerr_plan(sp, M, int(precision), cp, ptr(perm), ptr(rows), ptr(passes), ptr(klist),
                                 entries.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
-    return {"P": P, "Ppad": Ppad, "kw": kw, "rtm": rtm, "perm": perm, "passes": passes[:npass],
-            "klist": klist[:nk_list], "entries": {"dense": entries[0], "multiplied": entries[1],
-                                                   "nonzero": entries[2]}}
+    return {"P": P, "Ppad": Ppad, "kw": kw, "rtm": rtm, "nrt": nrt, "perm": perm, "rows": rows,
+            "passes": passes[:npass], "klist": klist[:nk_list],
+            "entries": {"dense": entries[0], "multiplied": entries[1], "nonzero": entries[2]}}
 
 
 class Propagator:

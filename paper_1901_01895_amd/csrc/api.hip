@@ -389,7 +389,9 @@ size_t estimate_plan_bytes(const mmnlse_config &cfg) {
                     (!(cfg.flags & MMNLSE_KERR_GENERIC) && cfg.M >= 3 && sym);
   if (mfma) {
     const size_t P = M * (M + 1) / 2, Ppad = (P + 63) / 64 * 64;
-    b += Ppad * Ppad * 4 + Ppad * 12;  // FP32, or bf16 hi + lo: 4 bytes per entry either way; pair and offset tables
+    // FP32, or bf16 hi + lo: 4 bytes per entry either way, rows padded by up to a quarter;
+    // pair and offset tables
+    b += (Ppad + Ppad / 4) * Ppad * 4 + Ppad * 16;
   } else {
     b += M * M * M * M * sizeof(float);
   }
@@ -881,7 +883,7 @@ mmnlse_status mmnlse_footprint(const mmnlse_t h, size_t *bytes) {
 }
 
 mmnlse_status mmnlse_kerr_plan(const float *S, int32_t M, int32_t precision, int32_t *counts, int32_t *perm,
-                               int32_t *passes, int32_t *klist, double *entries) {
+                               int32_t *rows, int32_t *passes, int32_t *klist, double *entries) {
   g_err.clear();
   if (!S || !counts) return fail(MMNLSE_E_INVALID, "null argument");
   if (M < 1 || M > 256) return fail(MMNLSE_E_INVALID, "M must be in 1..256");
@@ -899,7 +901,9 @@ mmnlse_status mmnlse_kerr_plan(const float *S, int32_t M, int32_t precision, int
   counts[3] = (int32_t)kp.klist.size();
   counts[4] = kp.kw;
   counts[5] = kp.rtm;
+  counts[6] = kp.nrt;
   if (perm) std::copy(kp.perm.begin(), kp.perm.end(), perm);
+  if (rows) std::copy(kp.rows.begin(), kp.rows.end(), rows);
   for (size_t i = 0; passes && i < kp.passes.size(); ++i) {
     passes[4 * i] = kp.passes[i].x;
     passes[4 * i + 1] = kp.passes[i].y;

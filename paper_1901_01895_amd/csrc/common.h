@@ -117,10 +117,11 @@ struct Plan {
   float *gain = nullptr;  // [M] span-end field gain exp(alpha_p span / 2) (span_steps > 0)
   // packed symmetric tensor (matrix-core path): rows r = (p<=n), cols q = (l<=m)
   int P = 0, Ppad = 0;
-  float *Sp = nullptr;          // [Ppad][Ppad] FP32, weight 2 for l<m folded in
+  int mfma_rows = 0;            // row slots of the contraction (row tiles x 32, padding included)
+  float *Sp = nullptr;          // [mfma_rows][Ppad] FP32, weight 2 for l<m folded in
   uint16_t *Sph = nullptr;      // bf16 hi of Sp
   uint16_t *Spl = nullptr;      // bf16 lo of Sp - hi
-  int32_t *pairs = nullptr;     // [Ppad] packed (a | b << 16) for r / q index -> (a,b)
+  int32_t *pairs = nullptr;     // [mfma_rows] packed (a | b << 16) of each row slot, -1 = padding
   int32_t *koff = nullptr;      // [Ppad][2] LDS byte offsets of (X_a, X_b) per q, kernel lane order
   int koff_tt = 0;              // tile width (samples) the offsets were built for
   int4 *passes = nullptr;       // [npass] (first row tile, tiles, k-list offset, k-list length)
@@ -147,8 +148,10 @@ struct Plan {
 // Host-side plan of the packed matrix-core contraction (kerr_plan.hip).
 struct KerrPlan {
   int P = 0, Ppad = 0, kw = 8, nk = 0, nrt = 0, rtm = 2;
-  std::vector<int> perm;             // [P] natural pair index at each position
-  std::vector<int> a, b;             // [Ppad] pair (a <= b) at each position, padding (0, 0)
+  std::vector<int> perm;             // [P] natural pair index at each column position
+  std::vector<int> a, b;             // [Ppad] column pair (a <= b) at each position, padding (0, 0)
+  std::vector<int> rows;             // [nrt*32] natural pair index in each row slot, -1 = padding
+  std::vector<int> ra, rb;           // [nrt*32] row pair of each slot, padding (0, 0)
   std::vector<int4> passes;          // (first row tile, tiles, k-list offset, k-list length)
   std::vector<int32_t> klist;        // k-steps of each pass that hold a nonzero
   double entries[3] = {0, 0, 0};     // packed P*P, multiplied, nonzero

@@ -38,14 +38,14 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 struct MArgs {
   const float2 *src0, *src1, *src2;
   float2 *out0, *out1;
-  const float4 *A32;     // FP32 swizzle: [Ppad/32][Ppad/8][64] float4
-  const uint4 *Ah, *Al;  // bf16 swizzle: [Ppad/32][Ppad/16][64] 8 x bf16
-  const int *pairs;      // [Ppad] a | b << 16 (padding rows/cols -> (0,0), zero weight)
+  const float4 *A32;     // FP32 swizzle: [row tiles][Ppad/8][64] float4
+  const uint4 *Ah, *Al;  // bf16 swizzle: [row tiles][Ppad/16][64] 8 x bf16
+  const int *pairs;      // [P] per row slot a | b << 16, -1 for a padding row (zero weights)
   const int4 *koff;      // B operand: byte offsets of X_a, X_b rows in the LDS tile, lane order
   const int4 *passes;    // [npass] (first row tile, tiles, k-list offset, k-list length)
   const int *klist;      // k-steps of each pass that hold a nonzero entry of its rows
   float hg;
-  int M, T, P, Ppad, next, koff_tt, npass, rtm;
+  int M, T, P, Ppad, next, koff_tt, npass, rtm;  // P: row slots (row tiles x 32)
 };
 
 typedef float floatv2 __attribute__((ext_vector_type(2)));
@@ -106,9 +106,9 @@ __device__ __forceinline__ void scatter_tile(const MArgs &a, const floatx16 &cre
       if (half == h) {
         const int r = acc_row(v, h);
         const int i = rt * 32 + r;
-        if (i < a.P) {
-          const int4 q4 = pq[r >> 2];
-          const int ab = (r & 3) == 0 ? q4.x : (r & 3) == 1 ? q4.y : (r & 3) == 2 ? q4.z : q4.w;
+        const int4 q4 = pq[r >> 2];
+        const int ab = (r & 3) == 0 ? q4.x : (r & 3) == 1 ? q4.y : (r & 3) == 2 ? q4.z : q4.w;
+        if (i < a.P && ab >= 0) {
           const int p = ab & 0xffff, n = ab >> 16;
           const float2 C = make_float2(cre[v], cim[v]);
           Os[p * TT + col] = cfma_conj(Os[p * TT + col], C, Xs[n * TT + col]);
@@ -470,7 +470,7 @@ hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k) {
   a.hg = (float)(h * pl.gamma);
   a.M = pl.M;
   a.T = pl.T;
-  a.P = pl.P;
+  a.P = pl.mfma_rows;
   a.Ppad = pl.Ppad;
   a.next = k.next;
   if (pl.precision == MMNLSE_SPLIT_BF16) return go_w<1>(a, k.stage, pl.stream);
@@ -486,13 +486,19 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
   const bool split = pl.precision != MMNLSE_FP32;  // both bf16 modes share the tables
   KerrPlan kp;
   plan_kerr(S, M, split, kp);
-  const int P = kp.P, Ppad = kp.Ppad, nrt = kp.nrt, nk = kp.nk;
+  const int P = kp.P, Ppad = kp.Ppad, nrt = kp.nrt, nk = kp.nk, R = nrt * 32;
   pl.P = P;
   pl.Ppad = Ppad;
-  const int *a = kp.a.data(), *b = kp.b.data();
-  std::vector<int32_t> pairs(Ppad, 0);
-  for (int i = 0; i < P; ++i) pairs[i] = a[i] | (b[i] << 16);
-  auto Sp = [&](int r, int q) -> float { return r < P && q < P ? packed_entry(S, M, a[r], b[r], a[q], b[q]) : 0.f; };
+  pl.mfma_rows = R;
+  const int *a = kp.a.data(), *b = kp.b.data();  // columns
+  const int *rows = kp.rows.data(), *ra = kp.ra.data(), *rb = kp.rb.data();
+  std::vector<int32_t> pairs(R, -1);
+  for (int i = 0; i < R; ++i)
+    if (rows[i] >= 0) pairs[i] = ra[i] | (rb[i] << 16);
+  // row slot r, column position q
+  auto Sp = [&](int r, int q) -> float {
+    return rows[r] >= 0 && q < P ? packed_entry(S, M, ra[r], rb[r], a[q], b[q]) : 0.f;
+  };
   hipError_t e;
   auto alloc_copy = [&](void **dst, const void *src, size_t bytes) -> hipError_t {
     hipError_t r = hipMalloc(dst, bytes);
@@ -500,7 +506,7 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
     pl.bytes += bytes;
     return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
   };
-  if ((e = alloc_copy((void **)&pl.pairs, pairs.data(), sizeof(int32_t) * Ppad)) != hipSuccess) return e;
+  if ((e = alloc_copy((void **)&pl.pairs, pairs.data(), sizeof(int32_t) * R)) != hipSuccess) return e;
   // B-operand offsets (bytes into the LDS field tile [M][TT] float2) of X_a and
   // X_b for column q, in the order a lane reads them: split path q = 16 ks +
   // 8 half + e (natural order); FP32 path q = 8 kq + 2 s + half stored at
@@ -520,7 +526,7 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
   pl.koff_tt = TT;
   // swizzled A operand: each lane's MFMA A fragment of a (row tile, k-step) in one 16-byte load
   if (!split) {
-    std::vector<float> sw((size_t)Ppad * Ppad);
+    std::vector<float> sw((size_t)R * Ppad);
     for (int rt = 0; rt < nrt; ++rt)
       for (int kq = 0; kq < nk; ++kq)
         for (int lane = 0; lane < 64; ++lane)
@@ -528,7 +534,7 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
             sw[(((size_t)rt * nk + kq) * 64 + lane) * 4 + s] = Sp(rt * 32 + (lane & 31), 8 * kq + 2 * s + (lane >> 5));
     if ((e = alloc_copy((void **)&pl.Sp, sw.data(), sizeof(float) * sw.size())) != hipSuccess) return e;
   } else {
-    std::vector<uint16_t> hi((size_t)Ppad * Ppad), lo((size_t)Ppad * Ppad);
+    std::vector<uint16_t> hi((size_t)R * Ppad), lo((size_t)R * Ppad);
     for (int rt = 0; rt < nrt; ++rt)
       for (int ks = 0; ks < nk; ++ks)
         for (int lane = 0; lane < 64; ++lane)

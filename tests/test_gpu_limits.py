@@ -143,7 +143,9 @@ def test_kerr_work_counts(gpu_lib, name, kw):
           flush=True)
     assert work["dense"] == len(pairs) ** 2
     assert work["nonzero"] == nnz
-    assert nnz <= work["multiplied"] <= ((len(pairs) + 31) // 32 * 32) ** 2
+    plan = mm.kerr_plan(p.S, mm.FP32)
+    assert nnz <= work["multiplied"] <= 32 * plan["nrt"] * plan["Ppad"]
+    assert work["multiplied"] == plan["entries"]["multiplied"]
     P.close()
 
 
