@@ -297,11 +297,12 @@ mmnlse_status mmnlse_kerr_work(const mmnlse_t h, double *entries);
  * l < m) of a tensor symmetric in (l,m) and in (p,n), over P = M(M+1)/2
  * pairs, with the column order, the row tiles and the blocks (32 row slots
  * x one k-step of 8 columns FP32 / 16 split) that mmnlse_create would use.
- * counts (host, 7 ints, required): P, Ppad (P rounded up to 32: the padded
- * column count), number of passes, length of the k-list array, k-step width
- * in columns, largest number of row tiles per pass, number of row tiles.
- * The arrays may be NULL; when given they must hold: perm [P] (natural pair
- * index, in the order l <= m row-major, at each column position), rows
+ * counts (host, 7 ints, required): P, Ppad (column positions: at least P,
+ * a multiple of 32), number of passes, length of the k-list array, k-step
+ * width in columns, largest number of row tiles per pass, number of row
+ * tiles.  The arrays may be NULL; when given they must hold: perm [Ppad]
+ * (natural pair index, in the order l <= m row-major, at each column
+ * position, -1 for a zero padding column; every pair appears once), rows
  * [32 * row tiles] (natural pair index in each row slot, -1 for a zero
  * padding row; every pair appears once), passes [4 * number of passes]
  * (first row tile, row tiles, offset into klist, count), klist [length]

@@ -188,8 +188,8 @@ def problem_config(p, precision=FP32, generic=False, L=None, method=RK4IP, diag_
 
 def kerr_plan(S, precision: int = FP32) -> dict:
     """Host-only plan of the matrix-core contraction for tensor S [M,M,M,M]
-    (mmnlse_kerr_plan): column order, row tiles (slots with -1 padding),
-    passes of row tiles and their k-lists."""
+    (mmnlse_kerr_plan): column positions and row slots (natural pair index,
+    -1 for padding), passes of row tiles and their k-lists."""
     lib = load()
     S = np.ascontiguousarray(np.asarray(S, dtype=np.float32))
     M = S.shape[0]
@@ -198,7 +198,7 @@ def kerr_plan(S, precision: int = FP32) -> dict:
     cp = counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     _check(lib.mmnlse_kerr_plan(sp, M, int(precision), cp, None, None, None, None, None))
     P, Ppad, npass, nk_list, kw, rtm, nrt = (int(x) for x in counts)
-    perm = np.zeros(P, np.int32)
+    perm = np.zeros(Ppad, np.int32)
     rows = np.zeros(32 * nrt, np.int32)
     passes = np.zeros((max(npass, 1), 4), np.int32)
     klist = np.zeros(max(nk_list, 1), np.int32)

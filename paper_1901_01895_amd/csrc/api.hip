@@ -902,7 +902,7 @@ mmnlse_status mmnlse_kerr_plan(const float *S, int32_t M, int32_t precision, int
   counts[4] = kp.kw;
   counts[5] = kp.rtm;
   counts[6] = kp.nrt;
-  if (perm) std::copy(kp.perm.begin(), kp.perm.end(), perm);
+  if (perm) std::copy(kp.cols.begin(), kp.cols.end(), perm);
   if (rows) std::copy(kp.rows.begin(), kp.rows.end(), rows);
   for (size_t i = 0; passes && i < kp.passes.size(); ++i) {
     passes[4 * i] = kp.passes[i].x;

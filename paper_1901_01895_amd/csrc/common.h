@@ -148,7 +148,8 @@ struct Plan {
 // Host-side plan of the packed matrix-core contraction (kerr_plan.hip).
 struct KerrPlan {
   int P = 0, Ppad = 0, kw = 8, nk = 0, nrt = 0, rtm = 2;
-  std::vector<int> perm;             // [P] natural pair index at each column position
+  std::vector<int> perm;             // [P] sorted pair order (rows and columns are cut from it)
+  std::vector<int> cols;             // [Ppad] natural pair index at each column position, -1 = padding
   std::vector<int> a, b;             // [Ppad] column pair (a <= b) at each position, padding (0, 0)
   std::vector<int> rows;             // [nrt*32] natural pair index in each row slot, -1 = padding
   std::vector<int> ra, rb;           // [nrt*32] row pair of each slot, padding (0, 0)

@@ -492,12 +492,13 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
   pl.mfma_rows = R;
   const int *a = kp.a.data(), *b = kp.b.data();  // columns
   const int *rows = kp.rows.data(), *ra = kp.ra.data(), *rb = kp.rb.data();
+  const int *cols = kp.cols.data();
   std::vector<int32_t> pairs(R, -1);
   for (int i = 0; i < R; ++i)
     if (rows[i] >= 0) pairs[i] = ra[i] | (rb[i] << 16);
   // row slot r, column position q
   auto Sp = [&](int r, int q) -> float {
-    return rows[r] >= 0 && q < P ? packed_entry(S, M, ra[r], rb[r], a[q], b[q]) : 0.f;
+    return rows[r] >= 0 && cols[q] >= 0 ? packed_entry(S, M, ra[r], rb[r], a[q], b[q]) : 0.f;
   };
   hipError_t e;
   auto alloc_copy = [&](void **dst, const void *src, size_t bytes) -> hipError_t {

@@ -123,12 +123,12 @@ void plan_kerr(const float *S, int M, bool split, KerrPlan &kp) {
         o[k / 64] |= 1ull << (k % 64);
       }
   }
-  std::vector<uint64_t>().swap(mask);
   // Row tiles: fixed runs of 32 rows, or, when that costs more, the cut of
   // the row order into tiles of 1..32 rows minimising the listed k-steps
   // plus kTilePenalty per tile (a tile's scatter and B formation cost about
   // that many k-steps of matrix-core work).
   constexpr int kTilePenalty = 2;
+  const bool cut_fp32 = !split && (double)nonzero < (double)P * P;
   std::vector<int> cut;  // tile boundaries in the row order
   {
     std::vector<uint64_t> u(kwords);
@@ -149,7 +149,7 @@ void plan_kerr(const float *S, int M, bool split, KerrPlan &kp) {
     // passes pair tiles to share the costlier bf16 B formation (measured on
     // the 36-mode tensor: FP32 3.22 -> 3.00 ms per step with the cut tiles,
     // split 1.62 -> 1.70)
-    if (!split && (double)nonzero < (double)P * P) {
+    if (cut_fp32) {
       for (int i = 0; i < P; ++i) {
         std::fill(u.begin(), u.end(), 0ull);
         for (int j = i + 1; j <= std::min(P, i + 32); ++j) {
@@ -177,17 +177,80 @@ void plan_kerr(const float *S, int M, bool split, KerrPlan &kp) {
   kp.rows.assign((size_t)nrt * 32, -1);
   kp.ra.assign((size_t)nrt * 32, 0);
   kp.rb.assign((size_t)nrt * 32, 0);
-  std::vector<uint8_t> occ((size_t)nrt * nk, 0);
+  // tiles holding a nonzero in each column (natural column index)
+  const int twords = (nrt + 63) / 64;
+  std::vector<uint64_t> ct((size_t)P * twords, 0);
   for (int t = 0; t < nrt; ++t)
     for (int i = cut[t]; i < cut[t + 1]; ++i) {
       const size_t slot = (size_t)t * 32 + (i - cut[t]);
       kp.rows[slot] = perm[i];
       kp.ra[slot] = na[perm[i]];
       kp.rb[slot] = nb[perm[i]];
-      for (int w = 0; w < kwords; ++w)
-        for (uint64_t bits = rk[(size_t)i * kwords + w]; bits; bits &= bits - 1)
-          occ[(size_t)t * nk + 64 * w + __builtin_ctzll(bits)] = 1;
+      const uint64_t *m = row(perm[i]);
+      for (int w = 0; w < words; ++w)
+        for (uint64_t bits = m[w]; bits; bits &= bits - 1)
+          ct[(size_t)(64 * w + __builtin_ctzll(bits)) * twords + t / 64] |= 1ull << (t % 64);
     }
+  std::vector<uint64_t>().swap(mask);
+  // Column positions: the sorted order in k-steps of kw columns or, with
+  // the cut row tiles, the cut of that order into k-steps of 1..kw columns
+  // (the other positions are zero padding columns) that minimises the listed
+  // (tile, k-step) blocks plus half a block per k-step.  Padded to a
+  // multiple of 32 positions.
+  std::vector<int> cols;
+  if (cut_fp32) {
+    std::vector<uint64_t> u(twords);
+    auto blocks = [&](int i, int j) {  // tiles listing the k-step of columns i .. j-1
+      std::fill(u.begin(), u.end(), 0ull);
+      for (int c = i; c < j; ++c)
+        for (int w = 0; w < twords; ++w) u[w] |= ct[(size_t)perm[c] * twords + w];
+      long n = 0;
+      for (int w = 0; w < twords; ++w) n += __builtin_popcountll(u[w]);
+      return n;
+    };
+    long fixed = 0;
+    for (int i = 0; i < P; i += kw) fixed += 2 * blocks(i, std::min(P, i + kw)) + 1;
+    std::vector<long> best(P + 1, -1);
+    std::vector<int> from(P + 1, 0);
+    best[0] = 0;
+    for (int i = 0; i < P; ++i)
+      for (int j = i + 1; j <= std::min(P, i + kw); ++j) {
+        const long c = best[i] + 2 * blocks(i, j) + 1;
+        if (best[j] < 0 || c < best[j]) {
+          best[j] = c;
+          from[j] = i;
+        }
+      }
+    if (best[P] < fixed) {
+      std::vector<int> cc;
+      for (int j = P; j > 0; j = from[j]) cc.push_back(j);
+      cc.push_back(0);
+      std::reverse(cc.begin(), cc.end());
+      for (size_t k = 0; k + 1 < cc.size(); ++k) {
+        for (int c = cc[k]; c < cc[k + 1]; ++c) cols.push_back(perm[c]);
+        while (cols.size() % kw) cols.push_back(-1);
+      }
+    }
+  }
+  if (cols.empty()) cols = perm;
+  while (cols.size() % 32) cols.push_back(-1);
+  kp.Ppad = (int)cols.size();
+  kp.nk = kp.Ppad / kw;
+  kp.cols = cols;
+  kp.a.assign(kp.Ppad, 0);
+  kp.b.assign(kp.Ppad, 0);
+  for (int j = 0; j < kp.Ppad; ++j)
+    if (cols[j] >= 0) {
+      kp.a[j] = na[cols[j]];
+      kp.b[j] = nb[cols[j]];
+    }
+  const int nkc = kp.nk;
+  std::vector<uint8_t> occ((size_t)nrt * nkc, 0);
+  for (int j = 0; j < kp.Ppad; ++j)
+    if (cols[j] >= 0)
+      for (int w = 0; w < twords; ++w)
+        for (uint64_t bits = ct[(size_t)cols[j] * twords + w]; bits; bits &= bits - 1)
+          occ[(size_t)(64 * w + __builtin_ctzll(bits)) * nkc + j / kw] = 1;
   // Row tiles per pass.  RTM = 4 halves the B formations per output row but
   // needs 128 accumulator registers, which costs the second wave per SIMD;
   // that wave exists only for M <= 64 (two 128-sample workgroups fit one
@@ -200,9 +263,9 @@ void plan_kerr(const float *S, int M, bool split, KerrPlan &kp) {
   // listed k-steps of tiles rt0 .. rt0+nt-1 (union of their nonzero blocks)
   auto listed = [&](int rt0, int nt, std::vector<int32_t> *out) {
     int len = 0;
-    for (int k = 0; k < nk; ++k) {
+    for (int k = 0; k < nkc; ++k) {
       bool any = false;
-      for (int t = 0; t < nt; ++t) any = any || occ[(size_t)(rt0 + t) * nk + k];
+      for (int t = 0; t < nt; ++t) any = any || occ[(size_t)(rt0 + t) * nkc + k];
       if (any) {
         ++len;
         if (out) out->push_back(k);
