@@ -48,7 +48,7 @@ typedef enum {
   MMNLSE_E_DEVICE = 3,      /* HIP runtime error */
   MMNLSE_E_NONFINITE = 4,   /* NaN or Inf found in an input or result */
   MMNLSE_E_BUSY = 5,        /* request not finished yet (serving) */
-  MMNLSE_E_UNSUPPORTED = 6, /* valid request this build does not implement */
+  MMNLSE_E_UNSUPPORTED = 6, /* valid request the library does not implement */
   MMNLSE_E_STEP = 7         /* adaptive stepping could not reach the end (step below
                                h_min, or max_trials used up) */
 } mmnlse_status;

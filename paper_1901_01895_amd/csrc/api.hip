@@ -526,7 +526,7 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
       if (e == hipErrorOutOfMemory) goto nomem;
       if (e == hipErrorNotSupported) {
         free_plan(pl);
-        return fail(MMNLSE_E_UNSUPPORTED, "matrix-core Kerr path not available in this build");
+        return fail(MMNLSE_E_UNSUPPORTED, "matrix-core Kerr path not available in this library");
       }
       goto dev;
     }
