@@ -12,7 +12,14 @@
  *       applied per mode in the frequency domain (Section 3.1);
  *   Kerr part: N_p = i gamma sum_{l,m,n} S_plmn A_l A_m conj(A_n), the
  *       general multimode form the paper cites in Section 2 (for M = 1 it is
- *       the paper's gamma |A|^2 A).
+ *       the paper's gamma |A|^2 A), or, with MMNLSE_KERR_MANAKOV, the
+ *       paper's own operator of Eq. (1), N_a = i gamma (sum_b kappa_ab
+ *       |A_b|^2) A_a.
+ *
+ * Also: the two split-step variants of Section 3.1 for comparison
+ * (mmnlse_method), fiber spans with loss-compensating amplifiers
+ * (mmnlse_config.span_km, Section 5), an adaptive step size from the
+ * step-doubling estimate, and a continuous-batching server.
  *
  * Conventions
  *   - Units: t in ps, z in km, power in W, beta_n in ps^n/km, gamma in 1/(W km).
