@@ -163,13 +163,23 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
       }
       return hipSuccess;
     };
+    // the last half step of a step and the first of the next one share one
+    // forward transform: A(z+h) = D Y and the next W0 = D D Y (four-step plans)
+    auto lin2 = [&](float2 *Y) -> hipError_t {
+      if (prof && (e = prof->record(prof->lin, pl.stream)) != hipSuccess) return e;
+      if ((e = launch_linear_twice(pl, E, Y, Y, W0)) != hipSuccess) return e;
+      return prof ? prof->record(prof->lin, pl.stream) : hipSuccess;
+    };
+    bool have_w0 = false;
     for (int64_t s = 0; s < n_steps; ++s) {
-      if ((e = lin1(A, W0)) != hipSuccess) return e;
+      if (!have_w0 && (e = lin1(A, W0)) != hipSuccess) return e;
       const float2 *Aend = A;  // first pass: the end-point phase taken at z
       for (int it = 0; it < kAgrawalPasses; ++it) {
-        float2 *out = it + 1 < kAgrawalPasses ? W1 : A;
+        const bool last = it + 1 == kAgrawalPasses;
+        float2 *out = last ? A : W1;
         if ((e = phase(Aend, out)) != hipSuccess) return e;
-        if ((e = lin1(out, out)) != hipSuccess) return e;
+        have_w0 = last && pl.four_step && s + 1 < n_steps;
+        if ((e = have_w0 ? lin2(out) : lin1(out, out)) != hipSuccess) return e;
         Aend = W1;
       }
     }

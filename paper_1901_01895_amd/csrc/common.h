@@ -166,6 +166,10 @@ int mfma_tile_width(int M, int T);
 hipError_t launch_linear(const Plan &pl, const float4 *E, const float2 *in0, float2 *out0,
                          const float2 *in1, float2 *out1);
 hipError_t launch_kerr(const Plan &pl, double h, const KerrLaunch &k);
+// out1 = D in, out2 = D D in (D = exp(h/2 L) from table E); in may be out1.  One
+// forward transform for both when the transform is four-step.
+hipError_t launch_linear_twice(const Plan &pl, const float4 *E, const float2 *in, float2 *out1,
+                               float2 *out2);
 // out = DA * exp(i (h gamma / 2) kappa (|Az|^2 + |Aend|^2)) (Manakov form, SSFM-Agrawal)
 hipError_t launch_manakov_phase(const Plan &pl, double h, const float2 *Az, const float2 *Aend,
                                 const float2 *DA, float2 *out);

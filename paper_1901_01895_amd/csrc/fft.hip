@@ -208,10 +208,14 @@ __global__ __launch_bounds__(NT) void linear_cols(LinArgs a) {
   }
 }
 
-// pass B: NB rows k1 of length N2: FFT, times E, inverse FFT
-template <int N2, int NB, int NT>
+// pass B: NB rows k1 of length N2: FFT, times E, inverse FFT.  DUAL (one
+// field, out[0]): also the spectrum times E a second time into out[1], i.e.
+// the propagator applied twice (E holds 1/T once, so the second factor is
+// E * T, exact for T = 2^k)
+template <int N2, int NB, int NT, bool DUAL>
 __global__ __launch_bounds__(NT) void linear_rows(LinArgs a) {
   __shared__ __align__(16) float2 buf[N2 * NB];
+  __shared__ __align__(16) float2 buf2[DUAL ? N2 * NB : 2];
   __shared__ float4 twl[N2];
   load_twiddles<N2, NT>(twl, a.tw, a.logT);
   const int job = blockIdx.y;
@@ -222,10 +226,19 @@ __global__ __launch_bounds__(NT) void linear_rows(LinArgs a) {
   for (int idx = 2 * threadIdx.x; idx < N2 * NB; idx += 2 * NT) st2(buf + idx, ld2(io + base + idx));
   __syncthreads();
   lds_fft<N2, NB, 1, N2, NT, false>(buf, twl, ilog2c(N2));
-  for (int idx = threadIdx.x; idx < N2 * NB; idx += NT) buf[idx] = cmul_hilo(buf[idx], a.E[base + idx]);
+  const float Tf = (float)a.T;
+  for (int idx = threadIdx.x; idx < N2 * NB; idx += NT) {
+    const float4 e = a.E[base + idx];
+    const float2 y = cmul_hilo(buf[idx], e);
+    buf[idx] = y;
+    if (DUAL) buf2[idx] = cmul_hilo(y, make_float4(e.x * Tf, e.y * Tf, e.z * Tf, e.w * Tf));
+  }
   __syncthreads();
   lds_fft<N2, NB, 1, N2, NT, true>(buf, twl, ilog2c(N2));
+  if (DUAL) lds_fft<N2, NB, 1, N2, NT, true>(buf2, twl, ilog2c(N2));
   for (int idx = 2 * threadIdx.x; idx < N2 * NB; idx += 2 * NT) st2(io + base + idx, ld2(buf + idx));
+  if (DUAL)
+    for (int idx = 2 * threadIdx.x; idx < N2 * NB; idx += 2 * NT) st2(a.out[1] + base + idx, ld2(buf2 + idx));
 }
 
 template <int L, int NB, int NT>
@@ -245,8 +258,10 @@ hipError_t go_cols(const LinArgs &a, int njobs, hipStream_t s, bool inv) {
 
 template <int N2, int NB, int NT>
 hipError_t go_rows(const LinArgs &a, int njobs, hipStream_t s) {
-  dim3 grid(a.M * (a.N1 / NB), njobs);
-  hipLaunchKernelGGL((linear_rows<N2, NB, NT>), grid, dim3(NT), 0, s, a);
+  // njobs == 0: the DUAL form on out[0] (outputs out[0] and out[1])
+  dim3 grid(a.M * (a.N1 / NB), njobs ? njobs : 1);
+  if (njobs) hipLaunchKernelGGL((linear_rows<N2, NB, NT, false>), grid, dim3(NT), 0, s, a);
+  else hipLaunchKernelGGL((linear_rows<N2, NB, NT, true>), grid, dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -316,6 +331,34 @@ hipError_t launch_linear(const Plan &pl, const float4 *E, const float2 *in0, flo
   e = rows_dispatch(a, njobs, pl.stream);
   if (e != hipSuccess) return e;
   return cols_dispatch(a, njobs, pl.stream, true);
+}
+
+hipError_t launch_linear_twice(const Plan &pl, const float4 *E, const float2 *in, float2 *out1,
+                               float2 *out2) {
+  if (!pl.four_step) {  // one LDS pass per application: two applications
+    hipError_t e = launch_linear(pl, E, in, out1, nullptr, nullptr);
+    if (e != hipSuccess) return e;
+    return launch_linear(pl, E, out1, out2, nullptr, nullptr);
+  }
+  for (const void *p : {(const void *)in, (const void *)out1, (const void *)out2})
+    if (reinterpret_cast<uintptr_t>(p) & 15) return hipErrorInvalidValue;  // entry points check first
+  LinArgs a;
+  a.in[0] = in;
+  a.out[0] = out1;
+  a.in[1] = out1;
+  a.out[1] = out2;
+  a.E = E;
+  a.tw = pl.tw;
+  a.M = pl.M;
+  a.T = pl.T;
+  a.logT = pl.logT;
+  a.N1 = pl.N1;
+  a.N2 = pl.N2;
+  hipError_t e = cols_dispatch(a, 1, pl.stream, false);  // in -> out1
+  if (e != hipSuccess) return e;
+  e = rows_dispatch(a, 0, pl.stream);                    // out1 -> out1 (E) and out2 (E twice)
+  if (e != hipSuccess) return e;
+  return cols_dispatch(a, 2, pl.stream, true);           // both, in place
 }
 
 }  // namespace mmnlse
