@@ -18,6 +18,8 @@
 //           transposed bin order), inverse FFT over k2
 //   pass C: times W_T^(-n2*k1), inverse FFT over k1 per column
 // All passes work in place, each workgroup owning disjoint elements.
+// launch_linear_twice applies D twice from one forward transform (pass A,
+// pass B writing the spectrum times E and times E twice, pass C on both).
 // The twiddles of an L-point transform in the four-step passes are the
 // entries W_L^j = W_T^(j T/L) of the table; a workgroup copies those L
 // entries to LDS first (at most 16 KB) so that its butterflies read them
