@@ -86,7 +86,7 @@ def cpu_baseline(p, seconds_target: float = 15.0, method: str = "rk4ip"):
     if getattr(p, "kappa", None) is not None:
         kern = oracle.KerrManakov(p.kappa.astype(np.float64), p.gamma)
     else:
-        kern = oracle.KerrPacked(p.S, p.gamma) if p.symmetric else oracle.KerrGeneric(p.S, p.gamma)
+        kern = oracle.KerrGeneric(p.S, p.gamma)
     step = {"rk4ip": oracle.rk4ip_step, "ssfm_rk4": oracle.ssfm_rk4_step,
             "ssfm_agrawal": oracle.ssfm_agrawal_step}[method]
     alpha = p.alpha if np.any(p.alpha) else None

@@ -132,7 +132,7 @@ def test_adaptive_multimode_matrix_core_path(gpu_lib):
     res, trials = P.propagate_adaptive(A, length, tol, 0.05)
     print(f"qpsk6 adaptive: {res}", flush=True)
     _check_against_oracle(p, p.A0, length, tol, 0.05, trials, A.cpu().numpy(),
-                          oracle.KerrPacked(p.S, p.gamma), 1e-5)
+                          oracle.KerrGeneric(p.S, p.gamma), 1e-5)
     P.close()
 
 

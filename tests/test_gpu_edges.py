@@ -52,7 +52,7 @@ def test_nonfinite_input_is_rejected_and_the_plan_survives(gpu_lib):
         P.propagate(bad)
     assert e.value.status == 4
     ref = oracle.propagate(p.A0, p.beta, None, p.S, p.gamma, p.dt, p.h, p.n_steps,
-                           kerr=oracle.KerrPacked(p.S, p.gamma))
+                           kerr=oracle.KerrGeneric(p.S, p.gamma))
     assert rel(P.propagate(p.A0), ref) < 1e-5
     P.close()
 

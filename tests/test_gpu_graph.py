@@ -61,7 +61,7 @@ def test_graph_propagation_matches_oracle(gpu_lib):
     P.propagate(p.A0)                        # warm
     out = P.propagate(p.A0)
     ref = oracle.propagate(p.A0, p.beta, None, p.S, p.gamma, p.dt, p.h, p.n_steps,
-                           kerr=oracle.KerrPacked(p.S, p.gamma))
+                           kerr=oracle.KerrGeneric(p.S, p.gamma))
     err = float(np.linalg.norm(out - ref) / np.linalg.norm(ref))
     print(f"qpsk6 T=2^12, 60 steps through the graph path: rel L2 {err:.3e}", flush=True)
     assert err < 1e-5

@@ -166,15 +166,36 @@ def test_power_reduction(gpu_lib):
     P.close()
 
 
+_REFS = {}
+
+
+def _oracle_field(p):
+    """The oracle's field after the problem's steps, generic Kerr form (the
+    plain definition: no symmetry of S used); computed once per problem."""
+    key = (p.name, p.M, p.T, p.n_steps)
+    if key not in _REFS:
+        _REFS[key] = oracle.propagate(p.A0, p.beta, None, p.S, p.gamma, p.dt, p.h, p.n_steps,
+                                      kerr=oracle.KerrGeneric(p.S, p.gamma))
+    return _REFS[key]
+
+
+def per_mode_rel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)
+
+
 def _propagate_parity(mm, p, tol, **kw):
     print(f"propagate {p.name} M={p.M} T={p.T} steps={p.n_steps} {kw}", flush=True)
     P = mm.Propagator.from_problem(p, **kw)
     out, st = P.propagate(p.A0, stats=True)
-    kern = oracle.KerrPacked(p.S, p.gamma) if p.symmetric else None
-    ref = oracle.propagate(p.A0, p.beta, None, p.S, p.gamma, p.dt, p.h, p.n_steps, kerr=kern)
+    ref = _oracle_field(p)
     err = rel(out, ref)
-    print(f"  rel L2 = {err:.3e}  kerr path = {P.kerr_path}", flush=True)
+    worst = float(per_mode_rel(out, ref).max())
+    print(f"  rel L2 = {err:.3e}, worst mode {worst:.3e}  kerr path = {P.kerr_path}", flush=True)
     assert err < tol
+    # every mode within the bar, not only the field as a whole
+    assert worst < tol
     assert st["steps"] == p.n_steps
     assert abs(st["power_in"] / oracle.power(p.A0.astype(np.complex64), p.dt) - 1) < 1e-12
     P.close()
@@ -300,7 +321,7 @@ def test_ssfm_rk4_propagation(gpu_lib, name, kw):
     p = W.make_problem(name, **kw)
     P = mm.Propagator.from_problem(p, method=mm.SSFM_RK4)
     out = P.propagate(p.A0)
-    kern = oracle.KerrPacked(p.S, p.gamma)
+    kern = oracle.KerrGeneric(p.S, p.gamma)
     ref = oracle.propagate(p.A0, p.beta, None, p.S, p.gamma, p.dt, p.h, p.n_steps, kerr=kern,
                            method="ssfm_rk4")
     err = rel(out, ref)

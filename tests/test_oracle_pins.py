@@ -15,7 +15,7 @@ import pytest
 
 import oracle
 from oracle import rk4ip as R
-from workloads import pair_exchange_tensor, soliton_problem, symmetric_gaussian_tensor
+from workloads import make_problem, pair_exchange_tensor, soliton_problem, symmetric_gaussian_tensor
 
 
 def _rel(a, b):
@@ -134,13 +134,30 @@ def test_kerr_conserves_power_exactly_for_pair_exchange_symmetry():
 
 
 def test_packed_equals_generic_for_symmetric_tensor():
-    for M in (1, 2, 5, 9):
+    for M in (1, 2, 5, 9, 15):
         rng = _rng(10 + M)
         S = symmetric_gaussian_tensor(M, rng)
-        X = _crandn(rng, M, 100)
+        X = _crandn(rng, M, 100 if M < 15 else 300)
         a = oracle.KerrPacked(S, 0.7, chunk=37)(X)
         b = oracle.KerrGeneric(S, 0.7, chunk=41)(X)
         assert _rel(a, b) < 1e-13
+        # every mode, not only the field as a whole
+        for p in range(M):
+            assert _rel(a[p], b[p]) < 1e-12
+
+
+def test_packed_equals_generic_for_masked_wdm36_tensor():
+    """The 36-mode tensor of the WDM workload (mode-group mask, 70 % of the
+    entries zero) on a few hundred samples of its launch field: the packed
+    form the 120-mode slice uses agrees with the plain definition here too."""
+    p = make_problem("wdm36", T=2 ** 10, n_steps=1)
+    assert p.meta["zero_fraction"] >= 0.7
+    X = p.A0[:, :320].astype(np.complex128)
+    a = oracle.KerrPacked(p.S, p.gamma, chunk=101)(X)
+    b = oracle.KerrGeneric(p.S, p.gamma, chunk=128)(X)
+    assert _rel(a, b) < 1e-13
+    for q in range(p.M):
+        assert _rel(a[q], b[q]) < 1e-12
 
 
 def test_packed_needs_only_lm_and_pn_symmetry():
@@ -269,6 +286,55 @@ def test_power_conservation_multimode_scheme():
         drifts.append(abs(oracle.power(out, dt) / oracle.power(A0, dt) - 1))
     assert drifts[1] < 1e-7
     assert drifts[0] / max(drifts[1], 1e-300) > 14.0
+
+
+def test_power_absolute_scale():
+    """dt * sum |A|^2 is the energy integral: a sech pulse sqrt(P0) sech(t/T0)
+    carries 2 P0 T0 (the window holds its tails to 1e-21), and a constant
+    field of power P over T samples carries P T dt."""
+    p = soliton_problem(noise=0.0)
+    P0, T0 = p.meta["P0"], p.meta["T0"]
+    assert abs(oracle.power(p.A0, p.dt) / (2.0 * P0 * T0) - 1.0) < 1e-12
+    A = np.full((3, 256), math.sqrt(0.37) * np.exp(0.3j))
+    assert abs(oracle.power(A, 0.125) / (0.37 * 3 * 256 * 0.125) - 1.0) < 1e-13
+
+
+def _varied_steps(n, z, seed):
+    """n positive step sizes in [0.5, 1.5] z/n, summing to z."""
+    r = np.random.default_rng((1901, seed)).uniform(0.5, 1.5, n)
+    return r * (z / r.sum())
+
+
+def test_propagate_steps_linear_part_exact_for_varied_steps():
+    """Without Kerr each RK4IP step of size h is exp(h/2 L) twice, so steps of
+    any sizes compose to the one-shot propagator exp(L sum h)."""
+    rng = _rng(31)
+    M, T, dt = 3, 256, 0.3
+    beta = np.column_stack([rng.uniform(-5, 5, M), rng.uniform(-3, 3, M), rng.uniform(-4, 4, M),
+                            rng.uniform(-1, 1, M)])
+    alpha = rng.uniform(0.0, 0.4, M)
+    A0 = _crandn(rng, M, T)
+    hs = _varied_steps(7, 1.3, 1)
+    out = oracle.propagate_steps(A0, beta, alpha, np.zeros((M,) * 4), 0.0, dt, hs)
+    w = oracle.angular_frequencies(T, dt)
+    exact = oracle.apply_linear(A0, oracle.half_step_propagator(w, beta, alpha, 2.0 * hs.sum()))
+    assert _rel(out, exact) < 1e-13
+
+
+def test_propagate_steps_soliton_with_varied_steps():
+    """The fundamental soliton over 1 km in 200 steps of sizes varying by a
+    factor three stays within the fourth-order error of fixed 5 m steps, and
+    equal steps give exactly the fixed-step propagation."""
+    p = soliton_problem(noise=0.0)
+    hs = _varied_steps(200, 1.0, 2)
+    out = oracle.propagate_steps(p.A0, p.beta, None, p.S, p.gamma, p.dt, hs)
+    t = oracle.time_grid(p.T, p.dt)
+    P0, T0 = p.meta["P0"], p.meta["T0"]
+    exact = math.sqrt(P0) / np.cosh(t / T0) * np.exp(0.5j * p.gamma * P0 * 1.0)
+    assert _rel(out[0], exact) < 2e-6
+    fixed = oracle.propagate(p.A0, p.beta, None, p.S, p.gamma, p.dt, 0.005, 200)
+    same = oracle.propagate_steps(p.A0, p.beta, None, p.S, p.gamma, p.dt, [0.005] * 200)
+    assert np.array_equal(fixed, same)
 
 
 def test_step_doubling_estimate_tracks_true_error():
@@ -698,3 +764,27 @@ def test_mutant_power_gain_fails_span_pin(monkeypatch):
                         lambda alpha, M, span: np.exp(np.asarray(alpha, dtype=np.float64) * span))
     out, seen, dispersed, alpha, z_span, k = _two_span_gaussian()
     assert _rel(out, dispersed(2 * z_span)) > 1e-3
+
+
+def test_mutant_one_propagator_for_all_steps_fails_varied_step_pins(monkeypatch):
+    """mistake: every step reuses the propagator of the first step size."""
+    def first_E(A0, beta, alpha, S, gamma, dt, hs, kerr=None):
+        A = np.array(A0, dtype=np.complex128, copy=True)
+        w = R.angular_frequencies(A.shape[1], dt)
+        N = R._kerr_for(S, gamma, kerr)
+        E = R.half_step_propagator(w, beta, alpha, hs[0])
+        for h in hs:
+            A = R.rk4ip_step(A, E, h, N)
+        return A
+    monkeypatch.setattr(R, "propagate_steps", first_E)
+    monkeypatch.setattr(oracle, "propagate_steps", first_E)
+    with pytest.raises(AssertionError):
+        test_propagate_steps_linear_part_exact_for_varied_steps()
+    with pytest.raises(AssertionError):
+        test_propagate_steps_soliton_with_varied_steps()
+
+
+def test_mutant_power_without_dt_fails_absolute_pin(monkeypatch):
+    monkeypatch.setattr(oracle, "power", lambda A, dt: float(np.sum(np.abs(np.asarray(A)) ** 2)))
+    with pytest.raises(AssertionError):
+        test_power_absolute_scale()
