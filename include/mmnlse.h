@@ -216,6 +216,29 @@ mmnlse_status mmnlse_kerr(mmnlse_t h, const void *X, void *Y);
  * Eq. (1) for alpha = 0 and a tensor with S_plmn == S_lpnm. */
 mmnlse_status mmnlse_power(mmnlse_t h, const void *X, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, serving loops and harnesses that forbid hipMalloc): the power of
+ * mmnlse_power without a handle and without any allocation or host sync.
+ * X: device complex64 array of n values (a field [M][T] has n = M*T) on the
+ * current device, 8-byte aligned; dt_ps: sample spacing (finite, > 0);
+ * out: device pointer to one double, 8-byte aligned, that receives
+ * dt_ps * sum |X|^2 computed in FP64.  Asynchronous on `stream` (a
+ * hipStream_t, NULL = the default stream).  For the same n and dt the value
+ * is bit-identical to mmnlse_power's (same blocks, same summation order).
+ * Scratch: a fixed device array of 1024 FP64 partial pairs (16 KiB) in the
+ * library, one per device, whose address is looked up on the first call on
+ * each device and which each device holds until the process ends.  Every
+ * call writes all the partials it reads, so nothing needs clearing, but all
+ * calls on one device share the array: calls that overlap on one device
+ * (several streams or threads) race and must be serialised by the caller.
+ * The partial count is n/4096 clamped to 1..1024, so every n up to
+ * MMNLSE_NOALLOC_MAX_VALUES fits the scratch.
+ * Errors: E_INVALID (null or misaligned pointer, n outside
+ * 1..MMNLSE_NOALLOC_MAX_VALUES, bad dt_ps; checked before any device call),
+ * E_DEVICE (no current device, symbol lookup or launch failure). */
+#define MMNLSE_NOALLOC_MAX_VALUES ((int64_t)1 << 40)
+mmnlse_status mmnlse_power_noalloc(const void *X, int64_t n, double dt_ps, double *out, void *stream);
+
 /* Step-doubling local error estimate (Richardson), RK4IP plans only
  * (E_UNSUPPORTED otherwise): from device field X,
  * takes two RK4IP steps of h and one step of 2h, and writes

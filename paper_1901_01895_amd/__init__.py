@@ -27,7 +27,8 @@ STATUS = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_DEVICE", 4: "E_NONFINITE"
 
 SYMBOLS = (
     "mmnlse_create", "mmnlse_destroy", "mmnlse_last_error", "mmnlse_propagate", "mmnlse_advance",
-    "mmnlse_amplify", "mmnlse_linear_half_step", "mmnlse_kerr", "mmnlse_power", "mmnlse_step_doubling",
+    "mmnlse_amplify", "mmnlse_linear_half_step", "mmnlse_kerr", "mmnlse_power", "mmnlse_power_noalloc",
+    "mmnlse_step_doubling",
     "mmnlse_synchronize", "mmnlse_footprint", "mmnlse_kerr_path", "mmnlse_profile",
     "mmnlse_propagate_adaptive", "mmnlse_kerr_work", "mmnlse_kerr_plan",
     "mmnlse_server_create", "mmnlse_server_submit", "mmnlse_server_poll", "mmnlse_server_wait",
@@ -110,6 +111,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.mmnlse_linear_half_step.argtypes = [vp, vp, vp]
     lib.mmnlse_kerr.argtypes = [vp, vp, vp]
     lib.mmnlse_power.argtypes = [vp, vp, dp]
+    lib.mmnlse_power_noalloc.argtypes = [vp, i64, ctypes.c_double, vp, vp]
     lib.mmnlse_step_doubling.argtypes = [vp, vp, dp]
     lib.mmnlse_synchronize.argtypes = [vp]
     lib.mmnlse_footprint.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
@@ -144,6 +146,18 @@ def _dptr(x) -> int:
     if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.complex64 and x.is_contiguous()):
         raise TypeError("expected a contiguous complex64 device tensor")
     return x.data_ptr()
+
+
+def power_noalloc(X, dt: float, out, stream=None) -> None:
+    """mmnlse_power_noalloc: writes dt * sum |X|^2 (FP64) into the one-element
+    float64 device tensor ``out``, asynchronously on ``stream`` (default:
+    torch's current stream), without allocating device memory."""
+    import torch
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64 and out.numel() >= 1):
+        raise TypeError("out must be a float64 device tensor")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(load().mmnlse_power_noalloc(ctypes.c_void_p(_dptr(X)), int(X.numel()), float(dt),
+                                       ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(s.cuda_stream)))
 
 
 def make_config(M, T, dt, beta, S, gamma, h, L, alpha=None, precision=FP32, symmetric=None,

@@ -543,7 +543,7 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
   }
   for (auto &b : pl->buf)
     if ((e = dev_alloc(*pl, (void **)&b, sizeof(float2) * MT)) != hipSuccess) goto nomem;
-  pl->red_n = (int)std::min<size_t>(1024, std::max<size_t>(1, MT / 4096));
+  pl->red_n = reduction_blocks(MT);
   if ((e = dev_alloc(*pl, (void **)&pl->red, sizeof(double2) * 1024)) != hipSuccess) goto nomem;
   if ((e = hipStreamSynchronize(pl->stream)) != hipSuccess) goto dev;  // tables ready, errors surfaced
   {

@@ -3,6 +3,9 @@
 // alpha = 0 and the Kerr tensor satisfies S_plmn == S_lpnm) and the
 // step-doubling estimate.
 
+#include <cmath>
+#include <mutex>
+
 #include "common.h"
 
 namespace mmnlse {
@@ -55,6 +58,26 @@ __global__ __launch_bounds__(RB) void norms(const float2 *__restrict__ x, const 
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// result = scale * sum_b partial[b].x, summed in block order (the order the
+// host loop of reduce_norms uses), so both give the same double
+__global__ void sum_partials(const double2 *__restrict__ partial, int nb, double scale, double *__restrict__ out) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double a = 0.0;
+    for (int i = 0; i < nb; ++i) a += partial[i].x;
+    out[0] = a * scale;
+  }
+}
+
+// Fixed device scratch of mmnlse_power_noalloc: the FP64 partial pairs of the
+// first pass.  Host code never passes `scratch` itself to a kernel: its
+// device address comes from hipGetSymbolAddress, per device.
+constexpr int kNoallocPartials = 1024;
+__device__ __align__(256) double2 scratch[kNoallocPartials];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double2 *g_scratch_ptr[kMaxDevices] = {};
+
 int grid_for(size_t n) {
   size_t b = (n + 255) / 256;
   return (int)(b < 4096 ? (b ? b : 1) : 4096);
@@ -79,6 +102,11 @@ hipError_t launch_amplify(const Plan &pl, float2 *A) {
   return hipGetLastError();
 }
 
+int reduction_blocks(size_t n) {
+  const size_t b = n / 4096;
+  return (int)(b < 1 ? 1 : (b > 1024 ? 1024 : b));
+}
+
 hipError_t reduce_norms(const Plan &pl, const float2 *x, const float2 *y, size_t n, double *sx,
                         double *sxy) {
   const int nb = pl.red_n;
@@ -101,3 +129,63 @@ hipError_t reduce_norms(const Plan &pl, const float2 *x, const float2 *y, size_t
 }
 
 }  // namespace mmnlse
+
+using namespace mmnlse;
+
+extern "C" mmnlse_status mmnlse_power_noalloc(const void *X, int64_t n, double dt_ps, double *out,
+                                              void *stream) {
+  set_last_error("");
+  if (!X || !out) {
+    set_last_error("null argument");
+    return MMNLSE_E_INVALID;
+  }
+  if (n <= 0 || n > MMNLSE_NOALLOC_MAX_VALUES) {
+    set_last_error("n must be in 1 .. " + std::to_string((long long)MMNLSE_NOALLOC_MAX_VALUES));
+    return MMNLSE_E_INVALID;
+  }
+  if (!(dt_ps > 0.0) || !std::isfinite(dt_ps)) {
+    set_last_error("dt_ps must be finite and positive");
+    return MMNLSE_E_INVALID;
+  }
+  if (((uintptr_t)X & 7) || ((uintptr_t)out & 7)) {
+    set_last_error("X and out must be 8-byte aligned");
+    return MMNLSE_E_INVALID;
+  }
+  const int nb = reduction_blocks((size_t)n);
+  if (nb > kNoallocPartials) {  // cannot happen with reduction_blocks' cap; kept as the size guard
+    set_last_error("reduction needs more partials than the scratch holds");
+    return MMNLSE_E_INVALID;
+  }
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+    set_last_error(std::string("hipGetDevice: ") + (e != hipSuccess ? hipGetErrorString(e) : "device index too large"));
+    return MMNLSE_E_DEVICE;
+  }
+  double2 *partial = nullptr;
+  {
+    // bind the scratch of this device once, with the device current
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+      void *ptr = nullptr;
+      e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !ptr) {
+        set_last_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        return MMNLSE_E_DEVICE;
+      }
+      g_scratch_ptr[dev] = (double2 *)ptr;
+    }
+    partial = g_scratch_ptr[dev];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // every one of the nb blocks writes its own partial: nothing to clear
+  hipLaunchKernelGGL(norms, dim3(nb), dim3(RB), 0, s, (const float2 *)X, (const float2 *)nullptr, (size_t)n,
+                     partial);
+  hipLaunchKernelGGL(sum_partials, dim3(1), dim3(64), 0, s, (const double2 *)partial, nb, dt_ps, out);
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_last_error(std::string("power_noalloc launch: ") + hipGetErrorString(e));
+    return MMNLSE_E_DEVICE;
+  }
+  return MMNLSE_OK;
+}

@@ -179,6 +179,8 @@ hipError_t launch_tabulate_E(const Plan &pl, double h, float4 *E);
 hipError_t launch_amplify(const Plan &pl, float2 *A);
 hipError_t launch_convert_c128_to_c64(const Plan &pl, const double2 *in, float2 *out, size_t n);
 hipError_t launch_convert_c64_to_c128(const Plan &pl, const float2 *in, double2 *out, size_t n);
+// blocks (and FP64 partial pairs) of the norm reduction over n values: n/4096 in 1..1024
+int reduction_blocks(size_t n);
 // FP64 sum of |x|^2 (and of |x - y|^2 when y != nullptr) -> host values (synchronises)
 hipError_t reduce_norms(const Plan &pl, const float2 *x, const float2 *y, size_t n, double *sx,
                         double *sxy);

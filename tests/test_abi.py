@@ -70,3 +70,17 @@ def test_create_rejects_bad_arguments_without_touching_the_gpu():
     c = make(precision=1, flags=0)
     assert lib.mmnlse_create(ctypes.byref(c), None, ctypes.byref(h)) == 1
     assert lib.mmnlse_destroy(None) == 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_power_noalloc_rejects_bad_arguments_without_touching_the_gpu():
+    """mmnlse_power_noalloc checks its arguments before any device call (the
+    pointers below are never dereferenced)."""
+    import paper_1901_01895_amd as mm
+    lib = mm.load()
+    x, o = ctypes.c_void_p(4096), ctypes.c_void_p(8192)
+    for args in ((None, 64, 1.0, o), (x, 64, 1.0, None), (x, 0, 1.0, o), (x, -1, 1.0, o),
+                 (x, (1 << 40) + 1, 1.0, o), (x, 64, 0.0, o), (x, 64, -2.0, o), (x, 64, float("nan"), o),
+                 (x, 64, float("inf"), o), (ctypes.c_void_p(4100), 64, 1.0, o), (x, 64, 1.0, ctypes.c_void_p(8196))):
+        assert lib.mmnlse_power_noalloc(*args, None) == 1, args
+        assert lib.mmnlse_last_error()
