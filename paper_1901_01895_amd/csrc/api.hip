@@ -76,6 +76,10 @@ static void free_plan(Plan *pl) {
   hipFree(pl->koff);
   hipFree(pl->passes);
   hipFree(pl->klist);
+  hipFree(pl->gtiles);
+  hipFree(pl->glist);
+  hipFree(pl->grange);
+  hipFree(pl->gkoff);
   for (auto &b : pl->buf) hipFree(b);
   for (auto &b : pl->sd) hipFree(b);
   hipFree(pl->red);

@@ -127,6 +127,13 @@ struct Plan {
   int4 *passes = nullptr;       // [npass] (first row tile, tiles, k-list offset, k-list length)
   int32_t *klist = nullptr;     // nonzero k-steps of each pass
   int npass = 0, mfma_rtm = 2;
+  // split-bf16 kernel with B formed once per workgroup (kerr_bf16.hip)
+  int ngroups = 0;              // 0: that kernel is not set up for this plan
+  int g_tt = 0;                 // its samples per workgroup
+  int32_t *gtiles = nullptr;    // [ngroups][4][rw] row tiles of each wave
+  int2 *glist = nullptr;        // k-list entries (k-step, per-wave slot masks)
+  int2 *grange = nullptr;       // [ngroups] (offset, length) into glist
+  int32_t *gkoff = nullptr;     // [Ppad/2] column modes (a, b), 8 bits each, two columns per word
   double kerr_entries[3] = {0, 0, 0};  // packed P*P, multiplied (listed blocks), nonzero
 
   // replayed step graph for launch-bound plans: `graph_steps` middle RK4IP
@@ -155,9 +162,27 @@ struct KerrPlan {
   std::vector<int> ra, rb;           // [nrt*32] row pair of each slot, padding (0, 0)
   std::vector<int4> passes;          // (first row tile, tiles, k-list offset, k-list length)
   std::vector<int32_t> klist;        // k-steps of each pass that hold a nonzero
+  std::vector<uint8_t> occ;          // [nrt][nk] 1 where the (row tile, k-step) block holds a nonzero
   double entries[3] = {0, 0, 0};     // packed P*P, multiplied, nonzero
 };
 void plan_kerr(const float *S, int M, bool split, KerrPlan &kp);
+
+// Row groups of the split-bf16 kernel that forms B once per workgroup
+// (kerr_bf16.hip): the row tiles are cut into groups of at most nw x rw
+// consecutive tiles, each wave of a workgroup owns up to rw tiles of a group,
+// and the group's k-list names every k-step where one of its tiles holds a
+// nonzero block, with a byte per wave marking which of that wave's tile
+// slots do.  Tiles are dealt to the waves to even out the blocks each wave
+// multiplies per chunk of kc listed k-steps (one barrier per chunk).
+struct KerrGroups {
+  int nw = 0, rw = 0, kc = 0, ngroups = 0;
+  std::vector<int32_t> tiles;  // [ngroups][nw][rw] row tile, -1 = empty slot
+  std::vector<int2> list;      // (k-step, masks): bit j of byte w = slot j of wave w is nonzero
+  std::vector<int2> range;     // [ngroups] (offset, length) into list
+  double blocks = 0;           // (tile, k-step) blocks multiplied
+  double chunk_max = 0;        // sum over chunks of the busiest wave's blocks
+};
+void plan_groups(const KerrPlan &kp, int nw, int rw, int kc, KerrGroups &g);
 float packed_entry(const float *S, int M, int ar, int br, int aq, int bq);
 // samples per workgroup of the matrix-core kernel for M modes and T samples
 int mfma_tile_width(int M, int T);

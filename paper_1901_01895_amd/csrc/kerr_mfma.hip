@@ -28,12 +28,12 @@
 #include <vector>
 
 #include "common.h"
+#include "mfma_util.h"
 
 namespace mmnlse {
 namespace {
 
-typedef float floatx16 __attribute__((ext_vector_type(16)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+using namespace mfma;
 
 struct MArgs {
   const float2 *src0, *src1, *src2;
@@ -47,78 +47,6 @@ struct MArgs {
   float hg;
   int M, T, P, Ppad, next, koff_tt, npass, rtm;  // P: row slots (row tiles x 32)
 };
-
-typedef float floatv2 __attribute__((ext_vector_type(2)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-
-// Two floats to bf16 (round to nearest even), packed in element order.
-__device__ __forceinline__ uint32_t to_bf16x2(float x0, float x1) {
-  return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatv2){x0, x1}, bf16x2));
-}
-
-// Two floats to bf16 hi (round to nearest even) and bf16 lo = bf16(x - hi),
-// each pair packed in one register in element order.
-__device__ __forceinline__ void split2(float x0, float x1, uint32_t &hi, uint32_t &lo) {
-  const uint32_t hb = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatv2){x0, x1}, bf16x2));
-  const float r0 = x0 - __builtin_bit_cast(float, hb << 16);
-  const float r1 = x1 - __builtin_bit_cast(float, hb & 0xffff0000u);
-  hi = hb;
-  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatv2){r0, r1}, bf16x2));
-}
-
-// B_q = X_a X_b at the lane's sample, X_a and X_b read at byte offsets oa, ob of
-// the lane's column base xb in the LDS field tile.
-__device__ __forceinline__ float2 form_b(const char *xb, int oa, int ob) {
-  const float2 xa = *(const float2 *)(xb + oa);
-  const float2 xc = *(const float2 *)(xb + ob);
-  return make_float2(fmaf(xa.x, xc.x, -xa.y * xc.y), fmaf(xa.x, xc.y, xa.y * xc.x));
-}
-
-// Output row of accumulator register v for lane-half `half` of a 32x32 tile.
-__device__ __forceinline__ int acc_row(int v, int half) { return 8 * (v >> 2) + 4 * half + (v & 3); }
-
-// Orders the LDS accesses made before it by some lanes of the wave against
-// those made after it by other lanes.  A wave's LDS operations complete in
-// issue order, so this only has to stop the compiler from moving, merging or
-// sinking per-lane code across it (it emits no instruction).
-__device__ __forceinline__ void wave_lds_order() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-template <int TT>
-__device__ __forceinline__ void scatter_tile(const MArgs &a, const floatx16 &cre, const floatx16 &cim,
-                                             int rt, const float2 *Xs, float2 *Os, int lane, int col) {
-  const int half = lane >> 5;
-  // the 32 (p, n) pairs of this row tile, loaded together before use
-  const int4 *pt = (const int4 *)(a.pairs + rt * 32);
-  int4 pq[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) pq[i] = pt[i];
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      // one lane-half at a time: its 32 lanes share the row, so the LDS
-      // read-modify-writes below touch 32 distinct samples; the two halves
-      // share the samples, so their updates must not overlap
-      if (half == h) {
-        const int r = acc_row(v, h);
-        const int i = rt * 32 + r;
-        const int4 q4 = pq[r >> 2];
-        const int ab = (r & 3) == 0 ? q4.x : (r & 3) == 1 ? q4.y : (r & 3) == 2 ? q4.z : q4.w;
-        if (i < a.P && ab >= 0) {
-          const int p = ab & 0xffff, n = ab >> 16;
-          const float2 C = make_float2(cre[v], cim[v]);
-          Os[p * TT + col] = cfma_conj(Os[p * TT + col], C, Xs[n * TT + col]);
-          if (p != n) Os[n * TT + col] = cfma_conj(Os[n * TT + col], C, Xs[p * TT + col]);
-        }
-      }
-      wave_lds_order();
-    }
-  }
-}
 
 // One pass over RT consecutive row tiles (rows 32*rt0 .. 32*(rt0+RT)-1) for
 // the wave's 32 samples: accumulate C over all q, then scatter into Os.  The
@@ -292,7 +220,7 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
     }
   }
 #pragma unroll
-  for (int j = 0; j < RT; ++j) scatter_tile<TT>(a, cre[j], cim[j], rt0 + j, Xs, Os, lane, col);
+  for (int j = 0; j < RT; ++j) scatter_tile<TT>(a.pairs, a.P, cre[j], cim[j], rt0 + j, Xs, Os, lane, col);
 }
 
 // Full contraction for one wave: the passes of the plan's pass table (runs of
@@ -450,7 +378,12 @@ float bf16_value(uint16_t b) {
 
 }  // namespace
 
+int bf16_group_tile_width(int M, int T);                // kerr_bf16.hip
+hipError_t setup_bf16_groups(Plan &pl, const KerrPlan &kp);
+hipError_t launch_kerr_bf16(const Plan &pl, double h, const KerrLaunch &k);
+
 hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k) {
+  if (pl.precision != MMNLSE_FP32 && pl.ngroups > 0) return launch_kerr_bf16(pl, h, k);
   MArgs a;
   a.src0 = k.src0;
   a.src1 = k.src1;
@@ -557,6 +490,10 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
   pl.npass = (int)kp.passes.size();
   pl.mfma_rtm = kp.rtm;
   for (int i = 0; i < 3; ++i) pl.kerr_entries[i] = kp.entries[i];
+  // split precisions: the kernel that forms B once per workgroup (kerr_bf16.hip)
+  // where it applies; MMNLSE_SPLIT_KERNEL=passes keeps the per-pass kernel above
+  const char *sk = std::getenv("MMNLSE_SPLIT_KERNEL");
+  if (split && !(sk && std::strcmp(sk, "passes") == 0)) return setup_bf16_groups(pl, kp);
   return hipSuccess;
 }
 

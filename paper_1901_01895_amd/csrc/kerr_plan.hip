@@ -308,6 +308,88 @@ void plan_kerr(const float *S, int M, bool split, KerrPlan &kp) {
   kp.entries[0] = (double)P * P;
   kp.entries[1] = executed;
   kp.entries[2] = nonzero;
+  kp.occ.swap(occ);
+}
+
+void plan_groups(const KerrPlan &kp, int nw, int rw, int kc, KerrGroups &g) {
+  const int nrt = kp.nrt, nk = kp.nk;
+  g = KerrGroups();
+  g.nw = nw;
+  g.rw = rw;
+  g.kc = kc;
+  if (nrt == 0) return;
+  const int cap = nw * rw;
+  const int ng = (nrt + cap - 1) / cap;
+  g.ngroups = ng;
+  g.tiles.assign((size_t)ng * nw * rw, -1);
+  auto occ = [&](int t, int k) { return (int)kp.occ[(size_t)t * nk + k]; };
+  for (int gi = 0; gi < ng; ++gi) {
+    const int t0 = (int)((long)gi * nrt / ng), t1 = (int)((long)(gi + 1) * nrt / ng), n = t1 - t0;
+    std::vector<int> ks;  // listed k-steps: some tile of the group holds a nonzero block
+    bool full = true;
+    for (int k = 0; k < nk; ++k) {
+      int c = 0;
+      for (int t = t0; t < t1; ++t) c += occ(t, k);
+      if (c) ks.push_back(k);
+      full = full && c == n;
+    }
+    // wave of each tile: dealt in turn, then pairwise swaps while they lower
+    // the sum over chunks of the busiest wave's block count
+    std::vector<int> wv(n);
+    for (int i = 0; i < n; ++i) wv[i] = i % nw;
+    auto cost = [&]() {
+      long tot = 0;
+      std::vector<int> per(nw);
+      for (size_t c0 = 0; c0 < ks.size(); c0 += kc) {
+        std::fill(per.begin(), per.end(), 0);
+        for (size_t c = c0; c < std::min(ks.size(), c0 + kc); ++c)
+          for (int i = 0; i < n; ++i) per[wv[i]] += occ(t0 + i, ks[c]);
+        tot += *std::max_element(per.begin(), per.end());
+      }
+      return tot;
+    };
+    long best = cost();
+    if (!full) {
+      // bounded local search (a few sweeps over the pairs of the group's tiles)
+      for (int sweep = 0; sweep < 8; ++sweep) {
+        bool better = false;
+        for (int i = 0; i < n; ++i)
+          for (int j = i + 1; j < n; ++j) {
+            if (wv[i] == wv[j]) continue;
+            std::swap(wv[i], wv[j]);
+            const long c = cost();
+            if (c < best) {
+              best = c;
+              better = true;
+            } else {
+              std::swap(wv[i], wv[j]);
+            }
+          }
+        if (!better) break;
+      }
+    }
+    g.chunk_max += (double)best;
+    std::vector<int> fill(nw, 0);
+    std::vector<int> slot_tile((size_t)nw * rw, -1);
+    for (int i = 0; i < n; ++i) {
+      const int w = wv[i], j = fill[w]++;
+      slot_tile[(size_t)w * rw + j] = t0 + i;
+      g.tiles[((size_t)gi * nw + w) * rw + j] = t0 + i;
+    }
+    g.range.push_back(make_int2((int)g.list.size(), (int)ks.size()));
+    for (int k : ks) {
+      uint32_t masks = 0;
+      for (int w = 0; w < nw; ++w)
+        for (int j = 0; j < rw; ++j) {
+          const int t = slot_tile[(size_t)w * rw + j];
+          if (t >= 0 && occ(t, k)) {
+            masks |= 1u << (8 * w + j);
+            g.blocks += 1;
+          }
+        }
+      g.list.push_back(make_int2(k, (int)masks));
+    }
+  }
 }
 
 }  // namespace mmnlse

@@ -1,0 +1,160 @@
+// Device helpers shared by the two matrix-core Kerr kernels (kerr_mfma.hip,
+// kerr_bf16.hip): operand conversions, forming B_q = X_l X_m from the LDS
+// field tile, and the mode-space scatter of a 32x32 accumulator tile.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.h"
+
+namespace mmnlse {
+namespace mfma {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatv2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+// Two floats to bf16 (round to nearest even), packed in element order.
+__device__ __forceinline__ uint32_t to_bf16x2(float x0, float x1) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((floatv2){x0, x1}, bf16x2));
+}
+
+// Two floats to bf16 hi (round to nearest even) and bf16 lo = bf16(x - hi),
+// each pair packed in one register in element order.
+__device__ __forceinline__ void split2(float x0, float x1, uint32_t &hi, uint32_t &lo) {
+  const uint32_t hb = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatv2){x0, x1}, bf16x2));
+  const float r0 = x0 - __builtin_bit_cast(float, hb << 16);
+  const float r1 = x1 - __builtin_bit_cast(float, hb & 0xffff0000u);
+  hi = hb;
+  lo = __builtin_bit_cast(uint32_t, __builtin_convertvector((floatv2){r0, r1}, bf16x2));
+}
+
+// B_q = X_a X_b at the lane's sample, X_a and X_b read at byte offsets oa, ob of
+// the lane's column base xb in the LDS field tile.
+__device__ __forceinline__ float2 form_b(const char *xb, int oa, int ob) {
+  const float2 xa = *(const float2 *)(xb + oa);
+  const float2 xc = *(const float2 *)(xb + ob);
+  return make_float2(fmaf(xa.x, xc.x, -xa.y * xc.y), fmaf(xa.x, xc.y, xa.y * xc.x));
+}
+
+// Output row of accumulator register v for lane-half `half` of a 32x32 tile.
+__device__ __forceinline__ int acc_row(int v, int half) { return 8 * (v >> 2) + 4 * half + (v & 3); }
+
+// Orders the LDS accesses made before it by some lanes of the wave against
+// those made after it by other lanes.  A wave's LDS operations complete in
+// issue order, so this only has to stop the compiler from moving, merging or
+// sinking per-lane code across it (it emits no instruction).
+__device__ __forceinline__ void wave_lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Mode-space epilogue of one 32-row tile rt of C (accumulators cre, cim of
+// a 32x32 MFMA tile, column = the lane's sample `col` of the LDS tiles of
+// width TT): for each row slot with pair (p, n),
+//   Os[p] += C conj(X_n),  and for p != n also  Os[n] += C conj(X_p).
+// pairs[slot] = p | n << 16, or -1 for a padding row; slots >= P are ignored.
+template <int TT>
+__device__ __forceinline__ void scatter_tile(const int *pairs, int P, const floatx16 &cre, const floatx16 &cim,
+                                             int rt, const float2 *Xs, float2 *Os, int lane, int col) {
+  const int half = lane >> 5;
+  // the 32 (p, n) pairs of this row tile, loaded together before use
+  const int4 *pt = (const int4 *)(pairs + rt * 32);
+  int4 pq[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) pq[i] = pt[i];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      // one lane-half at a time: its 32 lanes share the row, so the LDS
+      // read-modify-writes below touch 32 distinct samples; the two halves
+      // share the samples, so their updates must not overlap
+      if (half == h) {
+        const int r = acc_row(v, h);
+        const int i = rt * 32 + r;
+        const int4 q4 = pq[r >> 2];
+        const int ab = (r & 3) == 0 ? q4.x : (r & 3) == 1 ? q4.y : (r & 3) == 2 ? q4.z : q4.w;
+        if (i < P && ab >= 0) {
+          const int p = ab & 0xffff, n = ab >> 16;
+          const float2 C = make_float2(cre[v], cim[v]);
+          Os[p * TT + col] = cfma_conj(Os[p * TT + col], C, Xs[n * TT + col]);
+          if (p != n) Os[n * TT + col] = cfma_conj(Os[n * TT + col], C, Xs[p * TT + col]);
+        }
+      }
+      wave_lds_order();
+    }
+  }
+}
+
+}  // namespace mfma
+}  // namespace mmnlse
+
+namespace mmnlse {
+namespace mfma {
+
+// Exchanges the upper 32 lanes of a with the lower 32 lanes of b
+// (v_permlane32_swap): afterwards lanes 0..31 hold (a, b) = (own a, old a of
+// lane + 32) and lanes 32..63 hold (a, b) = (old b of lane - 32, own b).
+__device__ __forceinline__ void swap_halves(float &a, float &b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, a), __builtin_bit_cast(unsigned, b),
+                                                  false, false);
+  a = __builtin_bit_cast(float, (unsigned)r[0]);
+  b = __builtin_bit_cast(float, (unsigned)r[1]);
+}
+
+// Mode-space epilogue of one 32-row tile rt of C over 64 samples, given as
+// the accumulators of its two 32-sample column tiles (re0, im0: samples
+// 0..31, re1, im1: samples 32..63).  Swapping lane halves first gives every
+// lane l all 32 rows of sample l, so the lanes touch 64 distinct samples and
+// can update the LDS tiles (width 64) without ordering between them; the
+// rows are then walked in order, row (p, n) adding C conj(X_n) to Os[p] and,
+// for p != n, C conj(X_p) to Os[n].  Consecutive rows with the same p sum
+// into a register first.  pairs[slot] = p | n << 16, -1 = padding row.
+__device__ __forceinline__ void scatter_tile64(const int *pairs, floatx16 re0, floatx16 im0, floatx16 re1,
+                                               floatx16 im1, int rt, const float2 *__restrict__ Xs,
+                                               float2 *__restrict__ Os, int lane) {
+  constexpr int TT = 64;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    float a = re0[v], b = re1[v];
+    swap_halves(a, b);
+    re0[v] = a;
+    re1[v] = b;
+    a = im0[v];
+    b = im1[v];
+    swap_halves(a, b);
+    im0[v] = a;
+    im1[v] = b;
+  }
+  // row acc_row(v, 0) of the lane's sample is in (re0[v], im0[v]), row acc_row(v, 1) in (re1[v], im1[v])
+  const int *pt = pairs + rt * 32;
+  int cur = -1;
+  float2 acc = make_float2(0.f, 0.f), xp = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int r = 0; r < 32; ++r) {
+    const int v = (r >> 3) * 4 + (r & 3);
+    const bool upper = (r >> 2) & 1;
+    const float2 C = upper ? make_float2(re1[v], im1[v]) : make_float2(re0[v], im0[v]);
+    const int ab = pt[r];
+    if (ab >= 0) {
+      const int p = ab & 0xffff, n = ab >> 16;
+      if (p != cur) {
+        if (cur >= 0) Os[cur * TT + lane] = cadd(Os[cur * TT + lane], acc);
+        cur = p;
+        acc = make_float2(0.f, 0.f);
+        xp = Xs[p * TT + lane];
+      }
+      acc = cfma_conj(acc, C, Xs[n * TT + lane]);
+      if (p != n) Os[n * TT + lane] = cfma_conj(Os[n * TT + lane], C, xp);
+    }
+  }
+  if (cur >= 0) Os[cur * TT + lane] = cadd(Os[cur * TT + lane], acc);
+}
+
+}  // namespace mfma
+}  // namespace mmnlse
