@@ -44,6 +44,7 @@ WORKLOADS = {
                "8-ch WDM 16-QAM, Manakov/XPM operator of Eq. (1), alpha 0.23 dB/km, h=100 m",
 }
 METHODS = {"rk4ip": 0, "ssfm_rk4": 1, "ssfm_agrawal": 2}
+FULL_T = {"wdm36": 2 ** 16, "qpsk6": 2 ** 14, "soliton": 4096, "wdm120": 2 ** 17, "manakov": 2 ** 16}
 
 
 def manakov_flops_per_eval(M: int, T: int) -> float:
@@ -75,22 +76,19 @@ def linear_bytes_per_apply(M: int, T: int, four_step: bool) -> float:
     return M * T * (16.0 * passes + 16.0)
 
 
-def cpu_baseline(p, seconds_target: float = 15.0, method: str = "rk4ip"):
-    """Time the FP64 oracle on this host over a bounded number of steps."""
-    import oracle
+def cpu_model() -> str:
+    """CPU model name of this host (from /proc/cpuinfo)."""
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
-    if getattr(p, "kappa", None) is not None:
-        kern = oracle.KerrManakov(p.kappa.astype(np.float64), p.gamma)
-    else:
-        kern = oracle.KerrGeneric(p.S, p.gamma)
-    step = {"rk4ip": oracle.rk4ip_step, "ssfm_rk4": oracle.ssfm_rk4_step,
-            "ssfm_agrawal": oracle.ssfm_agrawal_step}[method]
-    alpha = p.alpha if np.any(p.alpha) else None
-    E = oracle.half_step_propagator(oracle.angular_frequencies(p.T, p.dt), p.beta, alpha, p.h)
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _time_oracle(p, kern, step, E, alpha, seconds_target: float):
     A = p.A0.astype(np.complex128)
     steps = 0
     t0 = time.perf_counter()
@@ -100,23 +98,53 @@ def cpu_baseline(p, seconds_target: float = 15.0, method: str = "rk4ip"):
         el = time.perf_counter() - t0
         if el > seconds_target or steps >= p.n_steps:
             break
+    return steps, el
+
+
+def cpu_baseline(p, seconds_target: float = 15.0, method: str = "rk4ip"):
+    """Time the FP64 oracle on this host over a bounded number of steps, with
+    numpy's BLAS on every core it may use and again on one thread."""
+    import oracle
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    if getattr(p, "kappa", None) is not None:
+        kern = oracle.KerrManakov(p.kappa.astype(np.float64), p.gamma)
+    else:
+        kern = oracle.KerrGeneric(p.S, p.gamma)
+    step = {"rk4ip": oracle.rk4ip_step, "ssfm_rk4": oracle.ssfm_rk4_step,
+            "ssfm_agrawal": oracle.ssfm_agrawal_step}[method]
+    alpha = p.alpha if np.any(p.alpha) else None
+    E = oracle.half_step_propagator(oracle.angular_frequencies(p.T, p.dt), p.beta, alpha, p.h)
+    steps, el = _time_oracle(p, kern, step, E, alpha, seconds_target)
+    with threadpool_limits(limits=1):
+        steps1, el1 = _time_oracle(p, kern, step, E, alpha, seconds_target / 2)
     v = p.M * p.T * steps / el
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        affinity = os.cpu_count() or 1
     return {"value": v, "unit": "mode*sample*steps/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{steps} {method} steps of the full {p.name} field (M={p.M}, T={p.T}), FP64 numpy, "
-                      f"{el:.1f} s"}
+                      f"{el:.1f} s",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity_cpus": affinity,
+            "blas_threads": int(threads),
+            "one_thread": {"value": p.M * p.T * steps1 / el1, "steps": steps1, "seconds": el1}}
 
 
-def serving(args):
+def serving(args, precision: str | None = None, rate: float | None = None):
     """Continuous-batching serving run: seeded Poisson request stream (M in {1,6,15,36},
-    T in {2^12,2^14,2^16}, L in {1,10,50} km) submitted at its arrival times."""
+    T in {2^12,2^14,2^16}, L in {1,10,50} km) submitted at its arrival times.
+    ``precision`` and ``rate`` default to the command line's."""
     import threading
 
     import paper_1901_01895_amd as mm
     import workloads as W
 
-    specs = W.serving_stream(args.requests, rate=args.rate)
+    precision = precision or args.precision
+    rate = args.rate if rate is None and args.workload == "serving" else rate
+    specs = W.serving_stream(args.requests, rate=rate)
     probs = [W.fiber.request_problem(sp) for sp in specs]
-    prec = precision_code(mm, args.precision)
+    prec = precision_code(mm, precision)
     cfgs = [mm.problem_config(p, precision=prec if p.M > 8 else mm.FP32) for p in probs]
     work = sum(p.M * p.T * p.n_steps for p in probs)
     lat = [None] * len(probs)
@@ -144,11 +172,11 @@ def serving(args):
         "metric": METRIC, "value": work / el, "unit": "mode*sample*steps/s", "n_gpus": 1,
         "steps": int(sum(p.n_steps for p in probs)), "warmup": 0, "ms_per_step": None,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": DTYPES[args.precision], "data": "synthetic",
+        "dtype": DTYPES[precision], "data": "synthetic",
         "config": {"workload": f"serving: {len(probs)} requests, Poisson rate "
-                               f"{'saturated' if args.rate is None else args.rate}/s, M in {{1,6,15,36}}, "
+                               f"{'saturated' if rate is None else rate}/s, M in {{1,6,15,36}}, "
                                "T in {2^12,2^14,2^16}, L in {1,10,50} km",
-                   "precision": args.precision, "steps_per_tick": args.steps_per_tick,
+                   "precision": precision, "steps_per_tick": args.steps_per_tick,
                    "streams": args.streams},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "max": float(lat.max())},
@@ -173,11 +201,26 @@ def main():
     ap.add_argument("--rate", type=float, default=None, help="serving: Poisson rate 1/s (default saturated)")
     ap.add_argument("--steps-per-tick", type=int, default=8)
     ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--no-serving", action="store_true",
+                    help="leave out the serving runs of the default report")
+    ap.add_argument("--serving-rate", type=float, default=3.6,
+                    help="Poisson rate 1/s of the default report's latency runs")
+    ap.add_argument("--summarize-stats", metavar="DIR",
+                    help="no GPU work: write the kernel-statistics record of a rocprofv3 --stats run")
+    ap.add_argument("--summarize-sq", nargs="+", metavar="DIR",
+                    help="no GPU work: write the SQ counter record of rocprofv3 --pmc runs")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no GPU work: write the HBM-traffic record of two rocprofv3 --pmc runs")
     args = ap.parse_args()
     if args.summarize_pmc:
         print(json.dumps(summarize_pmc(*args.summarize_pmc, args.workload, args.precision)))
+        return
+    if args.summarize_stats:
+        rec = summarize_stats(args.summarize_stats, args.workload, args.precision, args.steps, args.warmup)
+        print(json.dumps({k: v for k, v in rec.items() if k != "kernels"}))
+        return
+    if args.summarize_sq:
+        print(json.dumps(summarize_sq(args.summarize_sq, args.workload, args.precision)["ratios"]))
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -220,9 +263,33 @@ def main():
         if q != args.precision:
             out[q] = {k: r[k] for k in ("value", "ms_per_step", "roofline", "kernels")}
             out[q]["speedup_vs_" + args.precision] = r["value"] / main_run["value"]
+    if not args.no_serving and args.workload == "wdm36" and args.method == "rk4ip":
+        out["serving"] = serving_report(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds, args.method)
     print(json.dumps(out), flush=True)
+
+
+def serving_report(args) -> dict:
+    """The serving part of the metric beside the throughput line: the seeded
+    256-request stream saturated (every arrival at t = 0: throughput) and as a
+    Poisson stream at --serving-rate (p50/p99 latency), each with the plain FP32
+    and the split-bf16 contraction.  Progress goes to stderr."""
+    runs = []
+    for rate in (None, args.serving_rate):
+        for q in ("fp32", "split_bf16"):
+            r = serving(args, precision=q, rate=rate)
+            runs.append({"arrivals": "saturated" if rate is None else f"poisson {rate}/s", "precision": q,
+                         "value": r["value"], "unit": r["unit"], "latency_s": r["latency_s"],
+                         "wall_s": r["wall_s"], "ticks": r["server"]["rounds"]})
+            print(f"bench: serving {runs[-1]['arrivals']} {q}: {r['value']:.3e} {r['unit']}, "
+                  f"p50 {r['latency_s']['p50']:.3f} s, p99 {r['latency_s']['p99']:.3f} s", file=sys.stderr, flush=True)
+    head = next(r for r in runs if r["arrivals"] != "saturated" and r["precision"] == args.precision
+                ) if args.precision in ("fp32", "split_bf16") else runs[-1]
+    sat = next(r for r in runs if r["arrivals"] == "saturated" and r["precision"] == head["precision"])
+    return {"requests": args.requests, "precision": head["precision"], "latency_s": head["latency_s"],
+            "poisson_rate_per_s": args.serving_rate, "saturated_value": sat["value"], "unit": sat["unit"],
+            "runs": runs}
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, precision: str) -> dict:
@@ -274,6 +341,134 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, precision: str)
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
     return rec
+
+
+def csrc_digest() -> str:
+    """sha256 over the library's HIP sources (names and contents, sorted)."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1901_01895_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
+def _kerr_flops(workload: str, precision: str) -> tuple[float, float]:
+    """(algorithmic flops per Kerr evaluation, flops of the blocks the plan
+    multiplies) for a workload, from the host-only contraction plan."""
+    import paper_1901_01895_amd as mm
+    import workloads as W
+    p = W.make_problem(workload, T=256, n_steps=1)  # same tensor as the full field
+    plan = mm.kerr_plan(p.S, precision_code(mm, precision))
+    T = FULL_T[workload]
+    e = plan["entries"]
+    return kerr_flops_per_eval(p.M, T, e["nonzero"]), kerr_flops_per_eval(p.M, T, e["multiplied"])
+
+
+def kerr_kernel_precision(name: str):
+    """Precision of a matrix-core Kerr kernel from its template arguments
+    (kerr_mfma<W, R, SPLIT, ...>, kerr_bf16<TT, RW, NPART, KC, SPLIT, ...>), else None."""
+    import re
+    m = re.search(r"kerr_(mfma|bf16)<([^>]*)>", name)
+    if not m:
+        return None
+    args = [a.strip() for a in m.group(2).split(",")]
+    split = args[2] if m.group(1) == "mfma" else args[4]
+    return {"0": "fp32", "1": "split_bf16", "2": "split_bf16_s"}.get(split)
+
+
+def summarize_stats(stats_dir: str, workload: str, precision: str, steps: int, warmup: int) -> dict:
+    """Turn a rocprofv3 --kernel-trace --stats run of
+        bench.py --workload <w> --steps K --warmup W --no-cpu-baseline --no-serving
+    (every precision measured in one process, as in the default report) into
+    profiles/kerr_<p>_<w>_stats.json for precision p: the calls and average
+    duration of every kernel of the run, and the Kerr time per evaluation on
+    the basis of the bench line's roofline (the durations of p's Kerr kernels
+    over the 4 evaluations of every RK4IP step measure() made for p: W warmup,
+    K timed, K profiled)."""
+    import csv
+    import glob
+    rows = []
+    for f in glob.glob(os.path.join(stats_dir, "**", "*kernel_stats.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            rows.append({"name": r["Name"], "calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"]),
+                         "total_ns": float(r["TotalDurationNs"])})
+    if not rows:
+        raise SystemExit("no kernel_stats.csv under " + stats_dir)
+    kerr = [r for r in rows if kerr_kernel_precision(r["name"]) == precision]
+    lin = [r for r in rows if "linear_" in r["name"]]
+    if not kerr:
+        raise SystemExit(f"no {precision} Kerr kernels in {stats_dir}")
+    total_steps = warmup + 2 * steps
+    evals = 4 * total_steps
+    kerr_ms = sum(r["total_ns"] for r in kerr) * 1e-6
+    flops, xflops = _kerr_flops(workload, precision)
+    ms_eval = kerr_ms / evals
+    peak = FP32_PEAK_TFLOPS if precision == "fp32" else BF16_PEAK_TFLOPS
+    rec = {"workload": workload, "precision": precision, "csrc_sha256": csrc_digest(),
+           "command": (f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats --output-format csv "
+                       f"-d <dir> -o run -- python3 <repo>/bench.py --workload {workload} "
+                       f"--steps {steps} --warmup {warmup} --no-cpu-baseline --no-serving; "
+                       f"python3 bench.py --summarize-stats <dir> --workload {workload} --precision {precision} "
+                       f"--steps {steps} --warmup {warmup}"),
+           "rk4ip_steps": total_steps, "kerr_evals": evals,
+           "kerr_ms_per_step": kerr_ms / total_steps, "kerr_ms_per_eval": ms_eval,
+           "linear_ms_per_step": sum(r["total_ns"] for r in lin) * 1e-6 / total_steps,
+           "flops_per_eval": flops, "executed_flops_per_eval": xflops,
+           "achieved_tflops": flops / (ms_eval * 1e-3) / 1e12,
+           "executed_tflops": xflops / (ms_eval * 1e-3) / 1e12,
+           "peak_tflops": peak, "frac": flops / (ms_eval * 1e-3) / 1e12 / peak,
+           "kernels": sorted(rows, key=lambda r: -r["total_ns"])}
+    path = os.path.join(ROOT, "profiles", f"kerr_{precision}_{workload}_stats.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
+def summarize_sq(dirs: list[str], workload: str, precision: str) -> dict:
+    """SQ / GRBM counters of the Kerr kernels from rocprofv3 --pmc runs of the
+    bench (one counter set per run) into profiles/kerr_<p>_<w>_sq.json, with
+    per-wave ratios and the matrix-core busy fraction
+        SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs * 256 CUs * 4 SIMDs)."""
+    import csv
+    import glob
+    tot: dict = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if "kerr_" in r["Kernel_Name"]:
+                    tot[r["Counter_Name"]] = tot.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    if not tot:
+        raise SystemExit("no Kerr kernel counters under the given folders")
+    rec = {"workload": workload, "precision": precision, "csrc_sha256": csrc_digest(), "counters": tot}
+    wc = tot.get("SQ_WAVE_CYCLES")
+    ratios = {}
+    for k in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+              "SQ_ACTIVE_INST_ANY", "SQ_ACTIVE_INST_VMEM"):
+        if wc and k in tot:
+            ratios[k + "/SQ_WAVE_CYCLES"] = tot[k] / wc
+    if tot.get("SQ_INSTS_MFMA"):
+        ratios["SQ_INSTS_VALU/SQ_INSTS_MFMA"] = tot.get("SQ_INSTS_VALU", 0.0) / tot["SQ_INSTS_MFMA"]
+        ratios["SQ_INSTS_LDS/SQ_INSTS_MFMA"] = tot.get("SQ_INSTS_LDS", 0.0) / tot["SQ_INSTS_MFMA"]
+    if tot.get("GRBM_GUI_ACTIVE") and "SQ_VALU_MFMA_BUSY_CYCLES" in tot:
+        ratios["mfma_busy"] = tot["SQ_VALU_MFMA_BUSY_CYCLES"] / (tot["GRBM_GUI_ACTIVE"] / 8 * 256 * 4)
+    rec["ratios"] = ratios
+    path = os.path.join(ROOT, "profiles", f"kerr_{precision}_{workload}_sq.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
+def rocprof_record(workload: str, precision: str):
+    """The committed kernel-statistics summary for this workload and precision,
+    if it was taken on the current sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"kerr_{precision}_{workload}_stats.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    return rec if rec.get("csrc_sha256") == csrc_digest() else None
 
 
 def traffic_for(kernel: str, workload: str):
@@ -357,7 +552,15 @@ def measure(mm, W, p, precision: str, args) -> dict:
                 "evals_per_launch": evals_per_launch,
                 "flops_per_eval": kflops, "executed_tflops": exec_tflops,
                 "nonzero_fraction": work["nonzero"] / work["dense"] if work else 1.0,
-                "multiplied_fraction": work["multiplied"] / work["dense"] if work else 1.0}
+                "multiplied_fraction": work["multiplied"] / work["dense"] if work else 1.0,
+                "kerr_ms_per_eval": prof["kerr_ms"] / max(prof["kerr_evals"], 1)}
+        rec = rocprof_record(args.workload, precision) if args.method == "rk4ip" else None
+        if rec is not None:
+            # the committed rocprofv3 kernel statistics of the same sources, on
+            # the same basis (Kerr kernel time per evaluation)
+            roof["rocprof"] = {"kerr_ms_per_eval": rec["kerr_ms_per_eval"], "frac": rec["frac"],
+                               "events_over_rocprof": roof["kerr_ms_per_eval"] / rec["kerr_ms_per_eval"],
+                               "record": f"profiles/kerr_{precision}_{args.workload}_stats.json"}
     else:
         kname = "linear_half_step"
         roof = {"bound": "hbm", "achieved": lin_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",

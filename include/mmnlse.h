@@ -350,23 +350,26 @@ mmnlse_status mmnlse_kerr_path(const mmnlse_t h, int32_t *path);
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of propagation requests on one device.
  *
- * A worker thread admits queued requests in arrival order while the summed
+ * A planner thread admits queued requests in arrival order while the summed
  * device footprint of the admitted ones stays within the budget (and at most
- * max_active are resident), keeps each admitted field and its plan resident
- * on the device, and in every scheduling round advances each active request
- * by up to steps_per_tick RK4IP steps, spreading the requests over
- * n_streams HIP streams so that their kernels overlap on the device.  A
- * request that has taken its L/h steps is copied back and retired, which
- * frees its memory for the next admission.  A request advanced in chunks
- * does exactly the arithmetic of one mmnlse_propagate call, so its result
- * is bit-identical alone and in any mix.
+ * max_active are resident), and sets each one up (plan, field upload, input
+ * power) on a stream of its own.  A worker thread keeps every admitted field
+ * and its plan resident on the device and advances each request in ticks of
+ * up to steps_per_tick RK4IP steps on one of n_streams HIP streams, so that
+ * the kernels of different requests overlap on the device; each request's
+ * next tick is launched as soon as its previous one has completed (an event
+ * per request), independently of the other requests.  A request that has
+ * taken its L/h steps is copied back and retired, which frees its memory
+ * for the next admission.  A request advanced in ticks does exactly the
+ * arithmetic of one mmnlse_propagate call, so its result is bit-identical
+ * alone and in any mix.
  * ------------------------------------------------------------------------ */
 typedef struct {
   size_t mem_budget_bytes;  /* device bytes the admitted requests may hold together;
                                0 = 80 % of the free device memory at create */
   int32_t max_active;       /* requests resident at once; 0 = 32 */
   int32_t n_streams;        /* HIP streams (default priority) requests are spread over; 0 = 4 */
-  int32_t steps_per_tick;   /* RK4IP steps per active request per round; 0 = 8 */
+  int32_t steps_per_tick;   /* RK4IP steps per tick of a request; 0 = 8 */
 } mmnlse_server_config;
 
 typedef struct {
@@ -374,12 +377,12 @@ typedef struct {
   int32_t queued, active;
   size_t admitted_bytes;       /* footprint of the requests resident now */
   size_t peak_admitted_bytes;  /* largest admitted footprint seen */
-  int64_t rounds;              /* scheduling rounds run */
+  int64_t rounds;              /* ticks launched (over all requests) */
 } mmnlse_server_counters;
 
 typedef struct mmnlse_server *mmnlse_server_t;
 
-/* Start a server (and its worker thread) on the current HIP device.
+/* Start a server (and its planner and worker threads) on the current HIP device.
  * Errors: E_INVALID, E_NOMEM, E_DEVICE. */
 mmnlse_status mmnlse_server_create(const mmnlse_server_config *cfg, mmnlse_server_t *out);
 

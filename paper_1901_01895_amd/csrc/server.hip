@@ -1,17 +1,21 @@
 // Serving: continuous batching of RK4IP propagation requests on one device.
 //
-// A worker thread owns every device resource.  Each round it
-//   1. admits queued requests in arrival order while the admitted footprint
-//      stays within the budget and fewer than max_active are resident
-//      (creating the request's plan, uploading its field, taking the FP64
-//      input power);
-//   2. advances every resident request by up to steps_per_tick RK4IP steps,
-//      the requests spread round-robin over n_streams streams so that their
-//      kernels run concurrently on the device;
-//   3. retires requests that have taken all L/h steps: FP64 output power,
-//      copy back, plan freed, latency stamped, waiters woken.
+// Two host threads own the device work.
+//   * The planner admits queued requests in arrival order while the admitted
+//     footprint stays within the budget and fewer than max_active are
+//     resident, and for each one creates its plan, uploads its field and
+//     takes the FP64 input power, all on a stream of its own, so that plan
+//     set-up never holds up the requests already running.
+//   * The worker keeps every resident request moving: it launches up to
+//     steps_per_tick RK4IP steps of a request on one of n_streams serving
+//     streams and records an event after them; whenever a request's event has
+//     completed it launches the request's next tick, or retires it once all
+//     L/h steps are done (FP64 output power and copy back on a stream of the
+//     worker's own that waits only on that request's event).  A request
+//     never waits for the others' ticks, so short and long requests share the
+//     device without a common round.
 // Requests keep their own plan and work fields, and the step schedule
-// carries h N(A) across rounds (run_steps start/finish), so every result is
+// carries h N(A) across ticks (run_steps start/finish), so every result is
 // bit-identical to a lone mmnlse_propagate of the same request.
 
 #include <algorithm>
@@ -47,6 +51,10 @@ struct SReq {
   std::string err;
   mmnlse_t plan = nullptr;
   double2 *stage = nullptr;
+  hipStream_t stream = nullptr;  // serving stream of its ticks
+  hipEvent_t ev = nullptr;       // recorded after the tick in flight
+  bool inflight = false;
+  int64_t tick_steps = 0;        // steps of the tick in flight
   int64_t n_steps = 0, done_steps = 0;
   double p_in = 0, p_out = 0;
   clk::time_point t_submit, t_start, t_done;
@@ -60,17 +68,22 @@ struct mmnlse_server {
   int device = 0;
   size_t budget = 0;
   int max_active = 32, n_streams = 4, steps_per_tick = 8;
-  std::vector<hipStream_t> streams;
+  std::vector<hipStream_t> streams;    // serving streams (ticks)
+  hipStream_t plan_stream = nullptr;   // planner: plan set-up, upload, input power
+  hipStream_t retire_stream = nullptr; // worker: output power and copy back
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<SReq *> queue;
+  std::condition_variable cv_work, cv_done, cv_plan;
+  std::deque<SReq *> queue;            // submitted, not yet admitted
+  std::deque<SReq *> ready;            // planned by the planner, not yet taken by the worker
   std::unordered_map<uint64_t, SReq *> all;
-  std::vector<SReq *> active;  // worker thread only
+  std::vector<SReq *> active;          // worker thread only
   uint64_t next_ticket = 1;
-  bool stop = false;
+  bool stop = false, planner_done = false;
+  int resident = 0;                    // admitted and not finished
   size_t used = 0, peak = 0;
   int64_t submitted = 0, completed = 0, failed = 0, rounds = 0;
-  std::thread worker;
+  size_t rr = 0;                       // planner: next serving stream
+  std::thread planner, worker;
 };
 
 namespace {
@@ -87,12 +100,18 @@ void release(SReq *r) {
   r->plan = nullptr;
   if (r->stage) hipFree(r->stage);
   r->stage = nullptr;
+  if (r->ev) hipEventDestroy(r->ev);
+  r->ev = nullptr;
 }
 
 // Create the plan, upload the field (into the plan's third work field) and
-// take the input power.
+// take the input power, on stream st (synchronised before returning).
 void activate(SReq *r, hipStream_t st) {
   r->t_start = clk::now();
+  if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
+    req_error(r, MMNLSE_E_DEVICE, "event creation failed");
+    return;
+  }
   mmnlse_status e = mmnlse_create(&r->cfg, st, &r->plan);
   if (e != MMNLSE_OK) {
     req_error(r, e, mmnlse_last_error());
@@ -123,9 +142,15 @@ void activate(SReq *r, hipStream_t st) {
   r->done_steps = 0;
 }
 
-// Output power, copy back, free.
-void retire(SReq *r) {
+// Output power and copy back on stream st, after the request's last tick
+// (its event); synchronises st.
+void retire(SReq *r, hipStream_t st) {
   Plan &pl = *r->plan->pl;
+  pl.stream = st;
+  if (hipStreamWaitEvent(st, r->ev, 0) != hipSuccess) {
+    req_error(r, MMNLSE_E_DEVICE, "retire: stream wait failed");
+    return;
+  }
   const size_t MT = (size_t)pl.M * pl.T;
   float2 *field = pl.buf[2];
   hipError_t he = mmnlse::reduce_norms(pl, field, nullptr, MT, &r->p_out, nullptr);
@@ -154,74 +179,117 @@ void finish(mmnlse_server *s, SReq *r) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->used -= r->bytes;
+    --s->resident;
     r->state = 2;
     if (r->status == MMNLSE_OK) ++s->completed;
     else ++s->failed;
   }
   s->cv_done.notify_all();
+  s->cv_plan.notify_one();
+}
+
+void planner_main(mmnlse_server *s) {
+  hipSetDevice(s->device);
+  for (;;) {
+    SReq *r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_plan.wait(lk, [&] {
+        return s->stop || (!s->queue.empty() && s->resident < s->max_active &&
+                           s->used + s->queue.front()->bytes <= s->budget);
+      });
+      if (s->stop) {
+        s->planner_done = true;
+        break;
+      }
+      r = s->queue.front();
+      s->queue.pop_front();
+      s->used += r->bytes;
+      s->peak = std::max(s->peak, s->used);
+      ++s->resident;
+      r->state = 1;
+      r->stream = s->streams[s->rr++ % s->streams.size()];
+    }
+    activate(r, s->plan_stream);
+    if (r->plan) r->plan->pl->stream = r->stream;  // its ticks run on the serving stream
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->ready.push_back(r);
+    }
+    s->cv_work.notify_one();
+  }
+  s->cv_work.notify_one();
+}
+
+// Launch the next tick of r on its stream (up to steps_per_tick steps, cut at
+// a span end, where the amplifier acts and the next step starts afresh, as
+// in mmnlse_propagate) and record its event.
+void launch_tick(mmnlse_server *s, SReq *r) {
+  Plan &pl = *r->plan->pl;
+  const int64_t d = r->done_steps, sp = pl.span_steps;
+  int64_t n = std::min<int64_t>(s->steps_per_tick, r->n_steps - d);
+  if (sp > 0) n = std::min<int64_t>(n, sp - d % sp);
+  const bool first = d == 0 || (sp > 0 && d % sp == 0);
+  const bool span_end = sp > 0 && (d + n) % sp == 0;
+  const bool last = d + n == r->n_steps || span_end;
+  hipError_t e = mmnlse::run_steps(pl, pl.buf[2], n, pl.h, pl.E, pl.buf, nullptr, first, last);
+  if (e == hipSuccess && span_end) e = mmnlse::launch_amplify(pl, pl.buf[2]);
+  if (e == hipSuccess) e = hipEventRecord(r->ev, pl.stream);
+  if (e != hipSuccess) {
+    req_error(r, MMNLSE_E_DEVICE, std::string("steps: ") + hipGetErrorString(e));
+    return;
+  }
+  r->tick_steps = n;
+  r->inflight = true;
 }
 
 void worker_main(mmnlse_server *s) {
   hipSetDevice(s->device);
-  size_t rr = 0;
   for (;;) {
-    std::vector<SReq *> admit;
+    std::vector<SReq *> fresh;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty() || !s->active.empty(); });
-      if (s->stop && s->active.empty()) break;
-      while (!s->stop && !s->queue.empty() && (int)(s->active.size() + admit.size()) < s->max_active &&
-             s->used + s->queue.front()->bytes <= s->budget) {
-        SReq *r = s->queue.front();
-        s->queue.pop_front();
-        s->used += r->bytes;
-        s->peak = std::max(s->peak, s->used);
-        r->state = 1;
-        admit.push_back(r);
-      }
+      if (s->active.empty())
+        s->cv_work.wait(lk, [&] { return !s->ready.empty() || (s->stop && s->planner_done); });
+      if (s->active.empty() && s->ready.empty() && s->stop && s->planner_done) break;
+      fresh.assign(s->ready.begin(), s->ready.end());
+      s->ready.clear();
     }
-    for (SReq *r : admit) {
-      activate(r, s->streams[rr++ % s->streams.size()]);
+    for (SReq *r : fresh) {
       if (r->status != MMNLSE_OK) finish(s, r);
       else s->active.push_back(r);
     }
-    if (s->active.empty()) continue;
-    // one scheduling round: every resident request advances, streams in parallel
-    for (SReq *r : s->active) {
-      Plan &pl = *r->plan->pl;
-      // a round stops at a span end: the amplifier acts there and the next
-      // step starts afresh, as in mmnlse_propagate
-      const int64_t d = r->done_steps, sp = pl.span_steps;
-      int64_t n = std::min<int64_t>(s->steps_per_tick, r->n_steps - d);
-      if (sp > 0) n = std::min<int64_t>(n, sp - d % sp);
-      const bool first = d == 0 || (sp > 0 && d % sp == 0);
-      const bool span_end = sp > 0 && (d + n) % sp == 0;
-      const bool last = d + n == r->n_steps || span_end;
-      hipError_t e = mmnlse::run_steps(pl, pl.buf[2], n, pl.h, pl.E, pl.buf, nullptr, first, last);
-      if (e == hipSuccess && span_end) e = mmnlse::launch_amplify(pl, pl.buf[2]);
-      if (e != hipSuccess) req_error(r, MMNLSE_E_DEVICE, std::string("steps: ") + hipGetErrorString(e));
-      r->done_steps += n;
-    }
-    for (hipStream_t st : s->streams) {
-      hipError_t e = hipStreamSynchronize(st);
-      if (e != hipSuccess)
-        for (SReq *r : s->active)
-          if (r->plan->pl->stream == st) req_error(r, MMNLSE_E_DEVICE, std::string("round: ") + hipGetErrorString(e));
-    }
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      ++s->rounds;
-    }
+    bool progressed = !fresh.empty();
+    int64_t ticks = 0;
     std::vector<SReq *> still;
     for (SReq *r : s->active) {
-      if (r->status != MMNLSE_OK || r->done_steps >= r->n_steps) {
-        if (r->status == MMNLSE_OK) retire(r);
-        finish(s, r);
-      } else {
-        still.push_back(r);
+      if (r->inflight) {
+        const hipError_t q = hipEventQuery(r->ev);
+        if (q == hipErrorNotReady) {
+          still.push_back(r);
+          continue;
+        }
+        r->inflight = false;
+        progressed = true;
+        if (q != hipSuccess) req_error(r, MMNLSE_E_DEVICE, std::string("tick: ") + hipGetErrorString(q));
+        else r->done_steps += r->tick_steps;
       }
+      if (r->status != MMNLSE_OK || r->done_steps >= r->n_steps) {
+        if (r->status == MMNLSE_OK) retire(r, s->retire_stream);
+        finish(s, r);
+        continue;
+      }
+      launch_tick(s, r);
+      ++ticks;
+      still.push_back(r);
     }
     s->active.swap(still);
+    if (ticks) {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->rounds += ticks;
+    }
+    // nothing finished: give the device a moment before polling again
+    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
 }
 
@@ -304,7 +372,7 @@ mmnlse_status mmnlse_server_create(const mmnlse_server_config *cfg, mmnlse_serve
     }
     s->budget = fr / 10 * 8;
   }
-  for (int i = 0; i < s->n_streams; ++i) {
+  for (int i = 0; i < s->n_streams + 2; ++i) {
     hipStream_t st;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
       for (auto x : s->streams) hipStreamDestroy(x);
@@ -314,7 +382,12 @@ mmnlse_status mmnlse_server_create(const mmnlse_server_config *cfg, mmnlse_serve
     }
     s->streams.push_back(st);
   }
+  s->retire_stream = s->streams.back();
+  s->streams.pop_back();
+  s->plan_stream = s->streams.back();
+  s->streams.pop_back();
   s->worker = std::thread(worker_main, s);
+  s->planner = std::thread(planner_main, s);
   *out = s;
   return MMNLSE_OK;
 }
@@ -357,7 +430,7 @@ mmnlse_status mmnlse_server_submit(mmnlse_server_t s, const mmnlse_config *cfg, 
     ++s->submitted;
     *ticket = r->ticket;
   }
-  s->cv_work.notify_one();
+  s->cv_plan.notify_one();
   return MMNLSE_OK;
 }
 
@@ -396,6 +469,9 @@ mmnlse_status mmnlse_server_destroy(mmnlse_server_t s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
   }
+  // the planner stops admitting; the worker runs what is resident to the end
+  s->cv_plan.notify_all();
+  if (s->planner.joinable()) s->planner.join();
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
   for (auto &kv : s->all) {
@@ -403,6 +479,8 @@ mmnlse_status mmnlse_server_destroy(mmnlse_server_t s) {
     delete kv.second;
   }
   for (auto st : s->streams) hipStreamDestroy(st);
+  hipStreamDestroy(s->plan_stream);
+  hipStreamDestroy(s->retire_stream);
   delete s;
   return MMNLSE_OK;
 }
