@@ -220,7 +220,7 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
     }
   }
 #pragma unroll
-  for (int j = 0; j < RT; ++j) scatter_tile<TT>(a.pairs, a.P, cre[j], cim[j], rt0 + j, Xs, Os, lane, col);
+  for (int j = 0; j < RT; ++j) scatter_tile32<TT>(a.pairs, cre[j], cim[j], rt0 + j, Xs, Os, lane, col);
 }
 
 // Full contraction for one wave: the passes of the plan's pass table (runs of

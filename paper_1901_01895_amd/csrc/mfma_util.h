@@ -1,6 +1,6 @@
 // Device helpers shared by the two matrix-core Kerr kernels (kerr_mfma.hip,
 // kerr_bf16.hip): operand conversions, forming B_q = X_l X_m from the LDS
-// field tile, and the mode-space scatter of a 32x32 accumulator tile.
+// field tile, and the mode-space scatter of 32x32 accumulator tiles.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -53,44 +53,6 @@ __device__ __forceinline__ void wave_lds_order() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Mode-space epilogue of one 32-row tile rt of C (accumulators cre, cim of
-// a 32x32 MFMA tile, column = the lane's sample `col` of the LDS tiles of
-// width TT): for each row slot with pair (p, n),
-//   Os[p] += C conj(X_n),  and for p != n also  Os[n] += C conj(X_p).
-// pairs[slot] = p | n << 16, or -1 for a padding row; slots >= P are ignored.
-template <int TT>
-__device__ __forceinline__ void scatter_tile(const int *pairs, int P, const floatx16 &cre, const floatx16 &cim,
-                                             int rt, const float2 *Xs, float2 *Os, int lane, int col) {
-  const int half = lane >> 5;
-  // the 32 (p, n) pairs of this row tile, loaded together before use
-  const int4 *pt = (const int4 *)(pairs + rt * 32);
-  int4 pq[8];
-#pragma unroll
-  for (int i = 0; i < 8; ++i) pq[i] = pt[i];
-#pragma unroll
-  for (int v = 0; v < 16; ++v) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      // one lane-half at a time: its 32 lanes share the row, so the LDS
-      // read-modify-writes below touch 32 distinct samples; the two halves
-      // share the samples, so their updates must not overlap
-      if (half == h) {
-        const int r = acc_row(v, h);
-        const int i = rt * 32 + r;
-        const int4 q4 = pq[r >> 2];
-        const int ab = (r & 3) == 0 ? q4.x : (r & 3) == 1 ? q4.y : (r & 3) == 2 ? q4.z : q4.w;
-        if (i < P && ab >= 0) {
-          const int p = ab & 0xffff, n = ab >> 16;
-          const float2 C = make_float2(cre[v], cim[v]);
-          Os[p * TT + col] = cfma_conj(Os[p * TT + col], C, Xs[n * TT + col]);
-          if (p != n) Os[n * TT + col] = cfma_conj(Os[n * TT + col], C, Xs[p * TT + col]);
-        }
-      }
-      wave_lds_order();
-    }
-  }
-}
-
 }  // namespace mfma
 }  // namespace mmnlse
 
@@ -132,7 +94,16 @@ __device__ __forceinline__ void scatter_tile64(const int *pairs, floatx16 re0, f
     im1[v] = b;
   }
   // row acc_row(v, 0) of the lane's sample is in (re0[v], im0[v]), row acc_row(v, 1) in (re1[v], im1[v])
-  const int *pt = pairs + rt * 32;
+  const int4 *pt = (const int4 *)(pairs + rt * 32);
+  int pr[32];  // the tile's 32 pairs, wave-uniform
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int4 q = pt[i];
+    pr[4 * i] = __builtin_amdgcn_readfirstlane(q.x);
+    pr[4 * i + 1] = __builtin_amdgcn_readfirstlane(q.y);
+    pr[4 * i + 2] = __builtin_amdgcn_readfirstlane(q.z);
+    pr[4 * i + 3] = __builtin_amdgcn_readfirstlane(q.w);
+  }
   int cur = -1;
   float2 acc = make_float2(0.f, 0.f), xp = make_float2(0.f, 0.f);
 #pragma unroll
@@ -140,7 +111,7 @@ __device__ __forceinline__ void scatter_tile64(const int *pairs, floatx16 re0, f
     const int v = (r >> 3) * 4 + (r & 3);
     const bool upper = (r >> 2) & 1;
     const float2 C = upper ? make_float2(re1[v], im1[v]) : make_float2(re0[v], im0[v]);
-    const int ab = pt[r];
+    const int ab = pr[r];
     if (ab >= 0) {
       const int p = ab & 0xffff, n = ab >> 16;
       if (p != cur) {
@@ -154,6 +125,63 @@ __device__ __forceinline__ void scatter_tile64(const int *pairs, floatx16 re0, f
     }
   }
   if (cur >= 0) Os[cur * TT + lane] = cadd(Os[cur * TT + lane], acc);
+}
+
+}  // namespace mfma
+}  // namespace mmnlse
+
+namespace mmnlse {
+namespace mfma {
+
+// Mode-space epilogue of one 32-row tile rt of C for the wave's 32 samples
+// (column `col` of LDS tiles of width TT): the accumulator layout gives lane
+// half h the rows acc_row(v, h), v = 0..15.  The halves take turns (their
+// lanes share the samples); within a half every lane owns one sample, so its
+// rows are walked in order without ordering between lanes: row (p, n) adds
+// C conj(X_n) to Os[p] and, for p != n, C conj(X_p) to Os[n], consecutive
+// rows with the same p summed in a register first.  pairs[slot] = p | n << 16,
+// -1 = padding row.
+template <int TT>
+__device__ __forceinline__ void scatter_tile32(const int *pairs, const floatx16 &cre, const floatx16 &cim, int rt,
+                                               const float2 *__restrict__ Xs, float2 *__restrict__ Os, int lane,
+                                               int col) {
+  const int half = lane >> 5;
+  // the tile's 32 pairs, wave-uniform, read before the lane halves diverge
+  const int4 *pt = (const int4 *)(pairs + rt * 32);
+  int pr[32];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int4 q = pt[i];
+    pr[4 * i] = __builtin_amdgcn_readfirstlane(q.x);
+    pr[4 * i + 1] = __builtin_amdgcn_readfirstlane(q.y);
+    pr[4 * i + 2] = __builtin_amdgcn_readfirstlane(q.z);
+    pr[4 * i + 3] = __builtin_amdgcn_readfirstlane(q.w);
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    if (half == h) {
+      int cur = -1;
+      float2 acc = make_float2(0.f, 0.f), xp = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int ab = pr[acc_row(v, h)];
+        if (ab >= 0) {
+          const int p = ab & 0xffff, n = ab >> 16;
+          const float2 C = make_float2(cre[v], cim[v]);
+          if (p != cur) {
+            if (cur >= 0) Os[cur * TT + col] = cadd(Os[cur * TT + col], acc);
+            cur = p;
+            acc = make_float2(0.f, 0.f);
+            xp = Xs[p * TT + col];
+          }
+          acc = cfma_conj(acc, C, Xs[n * TT + col]);
+          if (p != n) Os[n * TT + col] = cfma_conj(Os[n * TT + col], C, xp);
+        }
+      }
+      if (cur >= 0) Os[cur * TT + col] = cadd(Os[cur * TT + col], acc);
+    }
+    wave_lds_order();
+  }
 }
 
 }  // namespace mfma
