@@ -156,7 +156,10 @@ typedef struct mmnlse_ctx *mmnlse_t;
  * the default stream); the handle does not own it.  Synchronises the stream
  * before returning.
  * Errors: E_INVALID (sizes, L/h, symmetry flag not satisfied, split precision
- * without MMNLSE_S_SYMMETRIC), E_NOMEM, E_DEVICE. */
+ * without MMNLSE_S_SYMMETRIC), E_NOMEM (device or host memory; when the
+ * environment variable MMNLSE_HOST_BYTES_LIMIT is set, set-ups whose host
+ * tables would exceed that many bytes are refused before any device call),
+ * E_DEVICE.  Never throws. */
 mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *out);
 
 /* Release everything create allocated.  NULL is accepted. */
@@ -190,6 +193,12 @@ mmnlse_status mmnlse_propagate(mmnlse_t h, const void *A_in, void *A_out, int32_
  * (on an internal stream; replayed on the handle's stream) -- the same
  * kernels in the same order, so the result is bit-identical to the eager
  * schedule.  The environment variable MMNLSE_GRAPH=0 disables this.
+ * Every call starts afresh from A: for RK4IP and SSFM-RK4 plans the result
+ * of several calls is bit-identical to one call over their steps; an
+ * SSFM-Agrawal plan on the four-step transform computes the first half step
+ * of a call's first step by itself (within a call, and within
+ * mmnlse_propagate and the server, it comes from the previous step's dual
+ * transform), so split calls differ from one call at FP32 rounding level.
  * Errors: E_INVALID, E_DEVICE (launch failure). */
 mmnlse_status mmnlse_advance(mmnlse_t h, void *A, int64_t n_steps);
 

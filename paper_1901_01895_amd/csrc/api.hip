@@ -174,7 +174,9 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
       if ((e = launch_linear_twice(pl, E, Y, Y, W0)) != hipSuccess) return e;
       return prof ? prof->record(prof->lin, pl.stream) : hipSuccess;
     };
-    bool have_w0 = false;
+    // W0 = D A is carried between calls like h N(A) on the RK4IP path: a call
+    // without `start` finds it left by the previous call without `finish`
+    bool have_w0 = !start && pl.four_step;
     for (int64_t s = 0; s < n_steps; ++s) {
       if (!have_w0 && (e = lin1(A, W0)) != hipSuccess) return e;
       const float2 *Aend = A;  // first pass: the end-point phase taken at z
@@ -182,7 +184,7 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
         const bool last = it + 1 == kAgrawalPasses;
         float2 *out = last ? A : W1;
         if ((e = phase(Aend, out)) != hipSuccess) return e;
-        have_w0 = last && pl.four_step && s + 1 < n_steps;
+        have_w0 = last && pl.four_step && (s + 1 < n_steps || !finish);
         if ((e = have_w0 ? lin2(out) : lin1(out, out)) != hipSuccess) return e;
         Aend = W1;
       }
@@ -422,14 +424,26 @@ extern "C" {
 
 const char *mmnlse_last_error(void) { return g_err.c_str(); }
 
-mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *out) {
-  g_err.clear();
-  if (!cfg || !out) return fail(MMNLSE_E_INVALID, "null argument");
-  *out = nullptr;
+}  // extern "C"
+
+// Host bytes the plan set-up builds in temporary tables at most: the
+// twiddles, and the generic tensor copy or the packed tensor with its plan.
+static size_t estimate_host_bytes(const mmnlse_config &cfg) {
+  const size_t M = (size_t)cfg.M, P = M * (M + 1) / 2;
+  return (size_t)cfg.T * sizeof(float4) + std::max(M * M * M * M * sizeof(float), 5 * P * P + 64 * P);
+}
+
+static mmnlse_status create_impl(const mmnlse_config *cfg, void *stream, mmnlse_t *out, Plan *&pl_out) {
   {
     std::string why;
     const mmnlse_status v = validate_config(*cfg, why);
     if (v != MMNLSE_OK) return fail(v, why);
+  }
+  // optional cap on the host memory of the set-up (checked before any device call)
+  if (const char *lim = std::getenv("MMNLSE_HOST_BYTES_LIMIT")) {
+    const double cap = std::atof(lim);
+    if (cap > 0 && (double)estimate_host_bytes(*cfg) > cap)
+      return fail(MMNLSE_E_NOMEM, "plan set-up needs more host memory than MMNLSE_HOST_BYTES_LIMIT allows");
   }
   const int M = cfg->M, T = cfg->T;
   const double nst = std::round(cfg->L_km / cfg->h_km);
@@ -437,6 +451,7 @@ mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *ou
   const bool sym = (cfg->flags & MMNLSE_S_SYMMETRIC) != 0;
   Plan *pl = new (std::nothrow) Plan();
   if (!pl) return fail(MMNLSE_E_NOMEM, "host allocation");
+  pl_out = pl;
   pl->M = M;
   pl->T = T;
   pl->logT = ilog2i(T);
@@ -568,6 +583,23 @@ dev:
   return hipfail(e, "create");
 }
 
+extern "C" mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *out) {
+  g_err.clear();
+  if (!cfg || !out) return fail(MMNLSE_E_INVALID, "null argument");
+  *out = nullptr;
+  Plan *pl = nullptr;
+  try {
+    return create_impl(cfg, stream, out, pl);
+  } catch (const std::bad_alloc &) {
+    // host tables (twiddles, tensor copies, the contraction plan) did not fit
+    if (pl && !*out) free_plan(pl);
+    (void)hipGetLastError();
+    return fail(MMNLSE_E_NOMEM, "host memory exhausted while building the plan's tables");
+  }
+}
+
+extern "C" {
+
 mmnlse_status mmnlse_destroy(mmnlse_t h) {
   if (!h) return MMNLSE_OK;
   if (h->pl && h->pl->stream) hipStreamSynchronize(h->pl->stream);
@@ -645,7 +677,16 @@ mmnlse_status mmnlse_propagate(mmnlse_t h, const void *A_in, void *A_out, int32_
       int64_t c = pl.n_steps - done;
       if (pl.diag_every > 0) c = std::min<int64_t>(c, pl.diag_every - done % pl.diag_every);
       if (pl.span_steps > 0) c = std::min<int64_t>(c, pl.span_steps - done % pl.span_steps);
-      if ((e = advance_steps(pl, state, c)) != hipSuccess) break;
+      if (pl.method == MMNLSE_SSFM_AGRAWAL) {
+        // carry the split step's shared transform across diagnostic points
+        // (not across a span end, where the amplifier changes the field)
+        const bool first = done == 0 || (pl.span_steps > 0 && done % pl.span_steps == 0);
+        const bool last = done + c == pl.n_steps || (pl.span_steps > 0 && (done + c) % pl.span_steps == 0);
+        e = run_steps(pl, state, c, pl.h, pl.E, pl.buf, nullptr, first, last);
+      } else {
+        e = advance_steps(pl, state, c);
+      }
+      if (e != hipSuccess) break;
       done += c;
       if (pl.span_steps > 0 && done % pl.span_steps == 0 && (e = launch_amplify(pl, state)) != hipSuccess)
         break;

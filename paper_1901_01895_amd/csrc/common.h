@@ -227,6 +227,8 @@ struct Prof {
 // computes it from A first, `finish` leaves it out after the last step.  A
 // propagation split into chunks (first chunk start, last chunk finish, the
 // work buffers kept between chunks) does exactly the arithmetic of one call.
+// The split-step schemes keep the same contract (SSFM-Agrawal carries the
+// first half step D A of the next step in work[0] on four-step plans).
 hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float4 *E,
                      float2 *const *work, Prof *prof = nullptr, bool start = true,
                      bool finish = true);

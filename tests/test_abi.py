@@ -84,3 +84,21 @@ def test_power_noalloc_rejects_bad_arguments_without_touching_the_gpu():
                  (x, 64, float("inf"), o), (ctypes.c_void_p(4100), 64, 1.0, o), (x, 64, 1.0, ctypes.c_void_p(8196))):
         assert lib.mmnlse_power_noalloc(*args, None) == 1, args
         assert lib.mmnlse_last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_create_reports_host_memory_exhaustion_without_touching_the_gpu(monkeypatch):
+    """A set-up whose host tables exceed MMNLSE_HOST_BYTES_LIMIT fails with
+    E_NOMEM before any device call (the same status a std::bad_alloc in the
+    set-up returns; nothing escapes the C boundary)."""
+    import numpy as np
+    import paper_1901_01895_amd as mm
+    import workloads as W
+    lib = mm.load()
+    p = W.make_problem("wdm36", T=2 ** 10, n_steps=1)
+    cfg, keep = mm.problem_config(p, precision=mm.SPLIT_BF16)
+    monkeypatch.setenv("MMNLSE_HOST_BYTES_LIMIT", "100000")
+    h = ctypes.c_void_p()
+    assert lib.mmnlse_create(ctypes.byref(cfg), None, ctypes.byref(h)) == 2
+    assert b"host memory" in lib.mmnlse_last_error()
+    assert not h.value

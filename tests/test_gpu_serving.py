@@ -120,3 +120,27 @@ def test_spans_and_manakov_requests_served_like_alone(gpu_lib):
         outs = [srv.wait(t)[0] for t in tickets]
     for o, r in zip(outs, ref):
         assert np.array_equal(o, r)
+
+
+def test_agrawal_requests_served_like_alone(gpu_lib):
+    """SSFM-Agrawal on the four-step transform (M = 30 rows, T = 2^12) shares
+    the last half step of a step with the first of the next; the server's
+    ticks (3 steps) and a span end (every 5 steps) carry or restart that
+    shared transform exactly as one propagation does: bit-identical results,
+    and so are propagations with diagnostics every 4 steps."""
+    mm = gpu_lib
+    man = W.manakov_problem(M=30, T=2 ** 12, n_steps=20)
+    reqs = [(man, 0.0), (man, 5 * man.h)]
+    ref = []
+    for p, span in reqs:
+        P = mm.Propagator.from_problem(p, method=mm.SSFM_AGRAWAL, span=span)
+        ref.append(P.propagate(p.A0))
+        P.close()
+        P = mm.Propagator.from_problem(p, method=mm.SSFM_AGRAWAL, span=span, diag_every=4)
+        assert np.array_equal(P.propagate(p.A0), ref[-1])
+        P.close()
+    with mm.Server(n_streams=2, steps_per_tick=3) as srv:
+        tickets = [srv.submit(p.A0, mm.problem_config(p, method=mm.SSFM_AGRAWAL, span=span)) for p, span in reqs]
+        outs = [srv.wait(t)[0] for t in tickets]
+    for o, r in zip(outs, ref):
+        assert np.array_equal(o, r)
