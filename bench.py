@@ -205,6 +205,9 @@ def main():
                     help="leave out the serving runs of the default report")
     ap.add_argument("--serving-rate", type=float, default=3.6,
                     help="Poisson rate 1/s of the default report's latency runs")
+    ap.add_argument("--full-length", action="store_true",
+                    help="run the workload's whole length (L/h steps) in FP32 and split-bf16 and report the FP64 "
+                         "power drift and the split-vs-FP32 difference (no throughput line)")
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="no GPU work: write the kernel-statistics record of a rocprofv3 --stats run")
     ap.add_argument("--summarize-sq", nargs="+", metavar="DIR",
@@ -240,6 +243,9 @@ def main():
         print(json.dumps(serving(args)), flush=True)
         return
     p = W.make_problem(args.workload)
+    if args.full_length:
+        print(json.dumps(full_length(mm, W, p, args)), flush=True)
+        return
     precs = [args.precision] if args.precision_only else \
         [args.precision] + [q for q in PRECISIONS if q != args.precision]
     runs = {}
@@ -268,6 +274,45 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, args.cpu_seconds, args.method)
     print(json.dumps(out), flush=True)
+
+
+def full_length(mm, W, p, args) -> dict:
+    """The whole propagation (L/h RK4IP steps) of the workload in FP32, split
+    bf16 (three products) and split-S: FP64 power in and out (conserved for
+    alpha = 0 and a symmetric tensor), wall time, and the relative L2
+    difference of each split result from the FP32 one.  Progress to stderr."""
+    import torch
+    A0 = torch.from_numpy(p.A0.astype(np.complex64)).cuda()
+    res, fields = {}, {}
+    chunk = max(1, p.n_steps // 10)
+    for q in ("fp32", "split_bf16", "split_bf16_s"):
+        P = mm.Propagator.from_problem(p, precision=precision_code(mm, q))
+        A = A0.clone()
+        pin = P.power(A)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < p.n_steps:
+            n = min(chunk, p.n_steps - done)
+            P.advance(A, n)
+            torch.cuda.synchronize()
+            done += n
+            print(f"bench: full length {p.name} {q}: step {done}/{p.n_steps} ({time.perf_counter() - t0:.0f} s)",
+                  file=sys.stderr, flush=True)
+        el = time.perf_counter() - t0
+        pout = P.power(A)
+        P.close()
+        fields[q] = A.cpu().numpy()
+        res[q] = {"steps": p.n_steps, "seconds": el, "ms_per_step": 1e3 * el / p.n_steps,
+                  "power_in_W_ps": pin, "power_out_W_ps": pout, "power_drift": pout / pin - 1.0}
+    ref = fields["fp32"].astype(np.complex128)
+    nref = np.linalg.norm(ref)
+    for q in ("split_bf16", "split_bf16_s"):
+        d = fields[q].astype(np.complex128) - ref
+        res[q]["rel_l2_vs_fp32"] = float(np.linalg.norm(d) / nref)
+        res[q]["worst_mode_rel_l2_vs_fp32"] = float(np.max(np.linalg.norm(d, axis=1) / np.linalg.norm(ref, axis=1)))
+    return {"workload": WORKLOADS.get(args.workload, args.workload), "M": p.M, "T": p.T, "h_km": p.h,
+            "L_km": p.h * p.n_steps, "results": res}
 
 
 def serving_report(args) -> dict:

@@ -127,13 +127,14 @@ struct Plan {
   int4 *passes = nullptr;       // [npass] (first row tile, tiles, k-list offset, k-list length)
   int32_t *klist = nullptr;     // nonzero k-steps of each pass
   int npass = 0, mfma_rtm = 2;
-  // split-bf16 kernel with B formed once per workgroup (kerr_bf16.hip)
+  // matrix-core kernel with B formed once per workgroup (kerr_group.hip)
   int ngroups = 0;              // 0: that kernel is not set up for this plan
   int g_tt = 0;                 // its samples per workgroup
   int32_t *gtiles = nullptr;    // [ngroups][4][rw] row tiles of each wave
   int2 *glist = nullptr;        // k-list entries (k-step, per-wave slot masks)
   int2 *grange = nullptr;       // [ngroups] (offset, length) into glist
-  int32_t *gkoff = nullptr;     // [Ppad/2] column modes (a, b), 8 bits each, two columns per word
+  int32_t *gkoff = nullptr;     // [Ppad/2] column modes (a, b), 8 bits each, two columns per word,
+                                // in the order the lane halves form them
   double kerr_entries[3] = {0, 0, 0};  // packed P*P, multiplied (listed blocks), nonzero
 
   // replayed step graph for launch-bound plans: `graph_steps` middle RK4IP
@@ -167,8 +168,8 @@ struct KerrPlan {
 };
 void plan_kerr(const float *S, int M, bool split, KerrPlan &kp);
 
-// Row groups of the split-bf16 kernel that forms B once per workgroup
-// (kerr_bf16.hip): the row tiles are cut into groups of at most nw x rw
+// Row groups of the matrix-core kernel that forms B once per workgroup
+// (kerr_group.hip): the row tiles are cut into groups of at most nw x rw
 // consecutive tiles, each wave of a workgroup owns up to rw tiles of a group,
 // and the group's k-list names every k-step where one of its tiles holds a
 // nonzero block, with a byte per wave marking which of that wave's tile

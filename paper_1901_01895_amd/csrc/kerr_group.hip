@@ -1,24 +1,26 @@
-// Split-bf16 packed Kerr contraction with the B operand formed once per
+// Packed Kerr contraction on matrix cores with the B operand formed once per
 // workgroup and k-step, shared by the workgroup's four waves.
 //
 // Same packed form as kerr_mfma.hip (Kerr term of Eq. 1 for a tensor
 // symmetric in (l,m) and in (p,n)):
 //   B_q(t) = X_l(t) X_m(t),  C_r(t) = sum_q Sp[r][q] B_q(t),
 //   N_p(t) = i gamma ( sum_{r=(p,n)} C_r conj(X_n) + sum_{r=(n,p), n<p} C_r conj(X_n) ).
-// Sp and B are split into bf16 hi + lo (lo = bf16(x - hi)) and multiplied as
-// hi*lo + lo*hi + hi*hi on v_mfma_f32_32x32x16_bf16 with FP32 accumulation
-// (SPLIT = 1), or with B rounded to bf16 once (SPLIT = 2: S hi*B + S lo*B).
+// SPLIT = 0: FP32 on v_mfma_f32_32x32x2_f32 (k-steps of 8 columns, four
+// products of depth 2).  SPLIT = 1: Sp and B split into bf16 hi + lo (lo =
+// bf16(x - hi)), multiplied as hi*lo + lo*hi + hi*hi on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation (k-steps of 16 columns);
+// SPLIT = 2: B rounded to bf16 once (S hi*B + S lo*B).
 //
 // Workgroup = 4 waves (one per SIMD) x 64 samples, two 32-sample column tiles,
-// so every A fragment loaded feeds 12 matrix-core products.  The row tiles of
-// Sp (32 rows each) are cut into groups of up to 4 x RW tiles; each wave owns
-// up to RW tiles of a group and keeps their accumulators in registers for the
-// whole k-loop.  The k-loop walks the group's listed k-steps (16 columns
-// each; those where some tile of the group holds a nonzero) in chunks of KC.
-// For every chunk the four waves form B = X_l X_m once for its columns and
-// the workgroup's samples, split into bf16 hi and lo in the MFMA B-operand
-// layout, into a double-buffered LDS area (one barrier per chunk), and each
-// wave multiplies those of its tiles whose block at the k-step holds a
+// so every A fragment loaded feeds both column tiles.  The row tiles of Sp
+// (32 rows each) are cut into groups of up to 4 x RW tiles; each wave owns up
+// to RW tiles of a group and keeps their accumulators in registers for the
+// whole k-loop.  The k-loop walks the group's listed k-steps (those where
+// some tile of the group holds a nonzero) in chunks of KC.  For every chunk
+// the four waves form B = X_l X_m once for its columns and the workgroup's
+// samples, in the MFMA B-operand layout (split into bf16 hi and lo on the
+// split paths), into a double-buffered LDS area (one barrier per chunk), and
+// each wave multiplies those of its tiles whose block at the k-step holds a
 // nonzero (bit masks of the plan).  Forming B costs one pass over the
 // columns per group instead of one per pass of one to four row tiles (the
 // vector-instruction load of kerr_mfma.hip's split path), and the A operand
@@ -32,11 +34,12 @@
 // on timing.  The RK4 stage prologue and epilogue are those of
 // kerr_mfma.hip.
 //
-// setup_bf16_groups enables the kernel only for tensors whose group blocks
-// are nearly all nonzero (dense tensors); strongly masked ones stay on the
+// setup_groups enables the kernel only for tensors whose group blocks are
+// nearly all nonzero (dense tensors); strongly masked ones stay on the
 // per-pass kernel, which skips their zero blocks at less cost.
 
 #include <algorithm>
+#include <cstdlib>
 #include <vector>
 
 #include "common.h"
@@ -53,10 +56,11 @@ constexpr int NW = 4;  // waves per workgroup
 struct GArgs {
   const float2 *src0, *src1, *src2;
   float2 *out0, *out1;
-  const uint4 *Ah, *Al;  // swizzled A operand: [row tiles][nk][64 lanes] 8 x bf16
+  const uint4 *Ah, *Al;  // split: swizzled A operand [row tiles][nk][64 lanes] 8 x bf16 (hi, lo)
+  const float4 *A32;     // FP32: swizzled A operand [row tiles][nk][64 lanes] 4 x float
   const int *pairs;      // [row slots] p | n << 16, -1 = padding row
-  const int4 *kmodes;    // [Ppad / 8]: modes (a, b) of 8 consecutive columns, 8 bits each
-                         // (column 2i+c of the group in byte 2c (a) and 2c+1 (b) of word i)
+  const int *kmodes;     // [nk][2 lane halves][NE / 2]: modes (a, b) of the NE columns a lane half
+                         // forms per k-step, 8 bits each, two columns per word (a, b, a', b')
   const int *gtiles;     // [ngroups][NW][RW] row tile of each wave slot, -1 = empty
   const int2 *glist;     // listed k-steps: (k-step, slot masks, byte w for wave w)
   const int2 *grange;    // [ngroups] (offset, length) into glist
@@ -106,7 +110,10 @@ template <int TT, int RW, int NPART, int KC, int SPLIT>
 __device__ __forceinline__ void contract(const GArgs &a, const float2 *Xs, float2 *Os, uint4 *Bs, int w,
                                          int lane) {
   constexpr int CT = TT / 32;                // 32-sample column tiles
-  constexpr int NOP = SPLIT == 1 ? 4 : 2;    // B operands per (k-step, column tile): rh, ih (, rl, il)
+  // B operands per (k-step, column tile), 16 bytes per lane each: split rh, ih
+  // (, rl, il) of 8 bf16; FP32 re, im of 4 floats (one per 32x32x2 product)
+  constexpr int NOP = SPLIT == 1 ? 4 : 2;
+  constexpr int NE = SPLIT ? 8 : 4;          // columns a lane half forms per k-step (k-step: 2 NE columns)
   constexpr int UPW = KC * CT / NW;          // (k-step, column tile) units each wave forms per chunk
   static_assert(UPW >= 1 && UPW * NW == KC * CT, "the chunk's units are shared evenly by the waves");
   static_assert(KC % 2 == 0, "the A-operand registers alternate between two sets");
@@ -138,28 +145,45 @@ __device__ __forceinline__ void contract(const GArgs &a, const float2 *Xs, float
         const int u = w + NW * i, ukk = u / CT, uct = u % CT;
         if (c * KC + ukk < len) {
           const char *xb = (const char *)(Xs + 32 * uct + (lane & 31));
-          uint32_t urh[4], url[4], uih[4], uil[4];
+          constexpr int sh = 3 + (TT == 64 ? 6 : 5);  // byte offset of mode row r in the tile: r * TT * 8
           const int ow[4] = {o[i].x, o[i].y, o[i].z, o[i].w};
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {  // elements 2k and 2k+1 of the lane's 8
-            constexpr int sh = 3 + (TT == 64 ? 6 : 5);  // byte offset of mode row r in the tile: r * TT * 8
-            const int q = ow[k];
-            const float2 b0 = form_b(xb, (q & 0xff) << sh, ((q >> 8) & 0xff) << sh);
-            const float2 b1 = form_b(xb, ((q >> 16) & 0xff) << sh, ((unsigned)q >> 24) << sh);
-            if (SPLIT == 1) {
-              split2(b0.x, b1.x, urh[k], url[k]);
-              split2(b0.y, b1.y, uih[k], uil[k]);
-            } else {
-              urh[k] = to_bf16x2(b0.x, b1.x);
-              uih[k] = to_bf16x2(b0.y, b1.y);
-            }
-          }
           uint4 *dst = Bs + ((buf * KC + ukk) * CT + uct) * NOP * 64 + lane;
-          dst[0] = make_uint4(urh[0], urh[1], urh[2], urh[3]);
-          dst[64] = make_uint4(uih[0], uih[1], uih[2], uih[3]);
-          if (SPLIT == 1) {
-            dst[128] = make_uint4(url[0], url[1], url[2], url[3]);
-            dst[192] = make_uint4(uil[0], uil[1], uil[2], uil[3]);
+          // elements 2k and 2k+1 of the lane's NE from word k, converted as they are formed
+          if (SPLIT == 0) {
+            float re[4], im[4];
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+              const int q = ow[k];
+              const float2 b0 = form_b(xb, (q & 0xff) << sh, ((q >> 8) & 0xff) << sh);
+              const float2 b1 = form_b(xb, ((q >> 16) & 0xff) << sh, ((unsigned)q >> 24) << sh);
+              re[2 * k] = b0.x;
+              im[2 * k] = b0.y;
+              re[2 * k + 1] = b1.x;
+              im[2 * k + 1] = b1.y;
+            }
+            dst[0] = __builtin_bit_cast(uint4, make_float4(re[0], re[1], re[2], re[3]));
+            dst[64] = __builtin_bit_cast(uint4, make_float4(im[0], im[1], im[2], im[3]));
+          } else {
+            uint32_t urh[4], url[4], uih[4], uil[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              const int q = ow[k];
+              const float2 b0 = form_b(xb, (q & 0xff) << sh, ((q >> 8) & 0xff) << sh);
+              const float2 b1 = form_b(xb, ((q >> 16) & 0xff) << sh, ((unsigned)q >> 24) << sh);
+              if (SPLIT == 1) {
+                split2(b0.x, b1.x, urh[k], url[k]);
+                split2(b0.y, b1.y, uih[k], uil[k]);
+              } else {
+                urh[k] = to_bf16x2(b0.x, b1.x);
+                uih[k] = to_bf16x2(b0.y, b1.y);
+              }
+            }
+            dst[0] = make_uint4(urh[0], urh[1], urh[2], urh[3]);
+            dst[64] = make_uint4(uih[0], uih[1], uih[2], uih[3]);
+            if (SPLIT == 1) {
+              dst[128] = make_uint4(url[0], url[1], url[2], url[3]);
+              dst[192] = make_uint4(uil[0], uil[1], uil[2], uil[3]);
+            }
           }
         }
       }
@@ -171,19 +195,30 @@ __device__ __forceinline__ void contract(const GArgs &a, const float2 *Xs, float
 #pragma unroll
       for (int i = 0; i < UPW; ++i) {
         const int e = min(c * KC + (w + NW * i) / CT, len - 1);
-        o[i] = a.kmodes[2 * L.at(e).x + half];
+        const int *km = a.kmodes + (2 * L.at(e).x + half) * (NE / 2);
+        if (NE == 8) {
+          o[i] = *(const int4 *)km;
+        } else {
+          const int2 v = *(const int2 *)km;
+          o[i] = make_int4(v.x, v.y, 0, 0);
+        }
       }
     };
     // A operand of entry e (clamped) for every slot of the wave, in register
     // set `set`; unconditional for the same reason (an empty slot reads tile 0)
-    uint4 ah[2][RW], al[2][RW];
+    uint4 ah[2][RW], al[2][RW];   // split: hi, lo
+    float4 af[2][RW];             // FP32
     auto load_a = [&](int e, int set) {
       const int ks = L.at(min(e, len - 1)).x;
 #pragma unroll
       for (int j = 0; j < RW; ++j) {
         const size_t off = ((size_t)max(tile[j], 0) * a.nk + ks) * 64 + lane;
-        ah[set][j] = a.Ah[off];
-        al[set][j] = a.Al[off];
+        if (SPLIT) {
+          ah[set][j] = a.Ah[off];
+          al[set][j] = a.Al[off];
+        } else {
+          af[set][j] = a.A32[off];
+        }
       }
     };
 
@@ -206,34 +241,62 @@ __device__ __forceinline__ void contract(const GArgs &a, const float2 *Xs, float
         if (e < len) {
           const int m = (L.at(e).y >> (8 * w)) & 0xff;
           const uint4 *src = Bs + ((c & 1) * KC + kk) * CT * NOP * 64 + lane;
-          bf16x8 rh[CT], ih[CT], rl[CT], il[CT];
+          if (SPLIT == 0) {
+            float4 br[CT], bi[CT];
 #pragma unroll
-          for (int ct = 0; ct < CT; ++ct) {
-            rh[ct] = __builtin_bit_cast(bf16x8, src[(ct * NOP + 0) * 64]);
-            ih[ct] = __builtin_bit_cast(bf16x8, src[(ct * NOP + 1) * 64]);
-            if (SPLIT == 1) {
-              rl[ct] = __builtin_bit_cast(bf16x8, src[(ct * NOP + 2) * 64]);
-              il[ct] = __builtin_bit_cast(bf16x8, src[(ct * NOP + 3) * 64]);
+            for (int ct = 0; ct < CT; ++ct) {
+              br[ct] = __builtin_bit_cast(float4, src[(ct * NOP + 0) * 64]);
+              bi[ct] = __builtin_bit_cast(float4, src[(ct * NOP + 1) * 64]);
             }
-          }
-          // the wave's tiles whose block at this k-step holds a nonzero
+            // the wave's tiles whose block at this k-step holds a nonzero;
+            // the k-step's 8 columns are 4 products of depth 2 (element s of
+            // the lane's A and B float4: columns 2s + lane half)
 #pragma unroll
-          for (int j = 0; j < RW; ++j)
-            if ((m >> j) & 1) {
-              const bf16x8 sh = __builtin_bit_cast(bf16x8, ah[kk & 1][j]);
-              const bf16x8 sl = __builtin_bit_cast(bf16x8, al[kk & 1][j]);
+            for (int j = 0; j < RW; ++j)
+              if ((m >> j) & 1) {
+                const float4 av = af[kk & 1][j];
 #pragma unroll
-              for (int ct = 0; ct < CT; ++ct) {
-                cre[j][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, rh[ct], cre[j][ct], 0, 0, 0);
-                cim[j][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, ih[ct], cim[j][ct], 0, 0, 0);
-                if (SPLIT == 1) {
-                  cre[j][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rl[ct], cre[j][ct], 0, 0, 0);
-                  cim[j][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, il[ct], cim[j][ct], 0, 0, 0);
+                for (int s4 = 0; s4 < 4; ++s4) {
+                  const float as = s4 == 0 ? av.x : s4 == 1 ? av.y : s4 == 2 ? av.z : av.w;
+#pragma unroll
+                  for (int ct = 0; ct < CT; ++ct) {
+                    const float brs = s4 == 0 ? br[ct].x : s4 == 1 ? br[ct].y : s4 == 2 ? br[ct].z : br[ct].w;
+                    const float bis = s4 == 0 ? bi[ct].x : s4 == 1 ? bi[ct].y : s4 == 2 ? bi[ct].z : bi[ct].w;
+                    cre[j][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(as, brs, cre[j][ct], 0, 0, 0);
+                    cim[j][ct] = __builtin_amdgcn_mfma_f32_32x32x2f32(as, bis, cim[j][ct], 0, 0, 0);
+                  }
                 }
-                cre[j][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rh[ct], cre[j][ct], 0, 0, 0);
-                cim[j][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, ih[ct], cim[j][ct], 0, 0, 0);
+              }
+          } else {
+            bf16x8 rh[CT], ih[CT], rl[CT], il[CT];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+              rh[ct] = __builtin_bit_cast(bf16x8, src[(ct * NOP + 0) * 64]);
+              ih[ct] = __builtin_bit_cast(bf16x8, src[(ct * NOP + 1) * 64]);
+              if (SPLIT == 1) {
+                rl[ct] = __builtin_bit_cast(bf16x8, src[(ct * NOP + 2) * 64]);
+                il[ct] = __builtin_bit_cast(bf16x8, src[(ct * NOP + 3) * 64]);
               }
             }
+            // the wave's tiles whose block at this k-step holds a nonzero
+#pragma unroll
+            for (int j = 0; j < RW; ++j)
+              if ((m >> j) & 1) {
+                const bf16x8 sh = __builtin_bit_cast(bf16x8, ah[kk & 1][j]);
+                const bf16x8 sl = __builtin_bit_cast(bf16x8, al[kk & 1][j]);
+#pragma unroll
+                for (int ct = 0; ct < CT; ++ct) {
+                  cre[j][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, rh[ct], cre[j][ct], 0, 0, 0);
+                  cim[j][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, ih[ct], cim[j][ct], 0, 0, 0);
+                  if (SPLIT == 1) {
+                    cre[j][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rl[ct], cre[j][ct], 0, 0, 0);
+                    cim[j][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, il[ct], cim[j][ct], 0, 0, 0);
+                  }
+                  cre[j][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rh[ct], cre[j][ct], 0, 0, 0);
+                  cim[j][ct] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, ih[ct], cim[j][ct], 0, 0, 0);
+                }
+              }
+          }
         }
       }
 #pragma unroll
@@ -261,7 +324,7 @@ __device__ __forceinline__ void contract(const GArgs &a, const float2 *Xs, float
 }
 
 template <int TT, int RW, int NPART, int KC, int SPLIT, int STAGE>
-__global__ __launch_bounds__(64 * NW) void kerr_bf16(GArgs a) {
+__global__ __launch_bounds__(64 * NW) void kerr_group(GArgs a) {
   constexpr int NT = 64 * NW;
   extern __shared__ float2 sh[];
   const int MT = a.M * TT;
@@ -340,18 +403,18 @@ constexpr int kTT = 64, kKC = 2;
 constexpr size_t kLdsMax = 160 * 1024;
 
 // LDS of a workgroup: field tile, NPART partial output tiles, two B buffers
-// (sized for the three-product split, the larger one)
+// (sized for the three-product split, the largest)
 size_t lds_bytes(int M, int npart) {
   return (size_t)(1 + npart) * M * kTT * sizeof(float2) + (size_t)2 * kKC * (kTT / 32) * 4 * 64 * sizeof(uint4);
 }
 
 // partial output tiles: as many as LDS holds (4, 2 or 1; 0 = does not fit)
-int bf16_partials(int M) {
+int group_partials(int M) {
   for (int n : {4, 2, 1})
     if (lds_bytes(M, n) <= kLdsMax) return n;
   return 0;
 }
-int bf16_tiles_per_wave(int M) { return bf16_partials(M) == 4 ? 4 : 3; }
+int group_tiles_per_wave(int M) { return group_partials(M) == 4 ? 4 : 3; }
 
 template <int TT, int RW, int NPART, int KC, int SPLIT>
 hipError_t go(const GArgs &a, KerrStage st, hipStream_t s) {
@@ -366,18 +429,18 @@ hipError_t go(const GArgs &a, KerrStage st, hipStream_t s) {
     return hipGetLastError();
   };
   switch (st) {
-    case STAGE_PLAIN: return launch(kerr_bf16<TT, RW, NPART, KC, SPLIT, STAGE_PLAIN>);
-    case STAGE_K2: return launch(kerr_bf16<TT, RW, NPART, KC, SPLIT, STAGE_K2>);
-    case STAGE_K3: return launch(kerr_bf16<TT, RW, NPART, KC, SPLIT, STAGE_K3>);
-    case STAGE_K4: return launch(kerr_bf16<TT, RW, NPART, KC, SPLIT, STAGE_K4>);
-    case STAGE_K23: return launch(kerr_bf16<TT, RW, NPART, KC, SPLIT, STAGE_K23>);
+    case STAGE_PLAIN: return launch(kerr_group<TT, RW, NPART, KC, SPLIT, STAGE_PLAIN>);
+    case STAGE_K2: return launch(kerr_group<TT, RW, NPART, KC, SPLIT, STAGE_K2>);
+    case STAGE_K3: return launch(kerr_group<TT, RW, NPART, KC, SPLIT, STAGE_K3>);
+    case STAGE_K4: return launch(kerr_group<TT, RW, NPART, KC, SPLIT, STAGE_K4>);
+    case STAGE_K23: return launch(kerr_group<TT, RW, NPART, KC, SPLIT, STAGE_K23>);
   }
   return hipErrorInvalidValue;
 }
 
 template <int SPLIT>
 hipError_t go_shape(const GArgs &a, KerrStage st, hipStream_t s) {
-  switch (bf16_partials(a.M)) {
+  switch (group_partials(a.M)) {
     case 4: return go<kTT, 4, 4, kKC, SPLIT>(a, st, s);
     case 2: return go<kTT, 3, 2, kKC, SPLIT>(a, st, s);
     default: return go<kTT, 3, 1, kKC, SPLIT>(a, st, s);
@@ -386,24 +449,28 @@ hipError_t go_shape(const GArgs &a, KerrStage st, hipStream_t s) {
 
 }  // namespace
 
-// Tile width of the group kernel for M modes and T samples (0: not used).
-int bf16_group_tile_width(int M, int T) { return bf16_partials(M) > 0 && T % kTT == 0 ? kTT : 0; }
-
-// Build the group tables of the kernel for plan pl (split precisions) from
-// the contraction plan kp; the A operand and pair tables of setup_mfma are
-// shared.  Leaves pl.ngroups == 0 when the kernel does not apply.
-hipError_t setup_bf16_groups(Plan &pl, const KerrPlan &kp) {
-  const int TT = bf16_group_tile_width(pl.M, pl.T);
-  if (!TT || kp.nrt == 0) return hipSuccess;
+// Build the group tables of the kernel for plan pl from the contraction plan
+// kp (FP32 or split, as kp was built); the A operand and pair tables of
+// setup_mfma are shared.  Leaves pl.ngroups == 0 when the kernel does not
+// apply: it needs 64 samples per workgroup, LDS for M modes, and a tensor
+// whose group blocks are nearly all nonzero.
+hipError_t setup_groups(Plan &pl, const KerrPlan &kp) {
+  const bool split = pl.precision != MMNLSE_FP32;
+  if (group_partials(pl.M) == 0 || pl.T % kTT != 0 || kp.nrt == 0) return hipSuccess;
+  if (const char *env = std::getenv("MMNLSE_GROUP_KERNEL")) {
+    if (env[0] == '0') return hipSuccess;
+  }
   KerrGroups g;
-  plan_groups(kp, NW, bf16_tiles_per_wave(pl.M), kKC, g);
+  plan_groups(kp, NW, group_tiles_per_wave(pl.M), kKC, g);
   // The kernel keeps the four waves of a workgroup in step (one barrier per
-  // chunk) and skips zero blocks only per wave and k-step, so a strongly
-  // masked tensor leaves it waiting on overheads that its few products do
-  // not cover; there the per-pass kernel of kerr_mfma.hip is faster
-  // (measured on the 70 %-masked 36-mode tensor: 2.04 vs 1.72 ms per step,
-  // where the blocks of a group's listed k-steps are 61 % nonzero).  It is
-  // used when at least 90 % of them are.
+  // chunk) and skips zero blocks only per wave and k-step, so on a strongly
+  // masked tensor the waves idle at the barriers behind the busiest one and
+  // on the branches around skipped blocks; there the per-pass kernel of
+  // kerr_mfma.hip is faster (measured on the 70 %-masked 36-mode tensor,
+  // whose group blocks are 61 % nonzero: split 2.04 vs 1.72 ms per step,
+  // FP32 3.53 vs 2.84).  The group kernel is used when at least 90 % of the
+  // blocks of the groups' listed k-steps are nonzero (dense 120-mode tensor:
+  // split 449 -> 297 ms per step, FP32 935 -> 893).
   double listed_blocks = 0;
   for (int gi = 0; gi < g.ngroups; ++gi) {
     int n = 0;
@@ -411,10 +478,18 @@ hipError_t setup_bf16_groups(Plan &pl, const KerrPlan &kp) {
     listed_blocks += (double)g.range[gi].y * n;
   }
   if (g.blocks < 0.9 * listed_blocks) return hipSuccess;
-  // column modes, 8 bits each: column q in byte 2 (q % 2) (a) and 2 (q % 2) + 1 (b) of word q / 2
-  std::vector<uint32_t> koff((size_t)kp.Ppad / 2, 0u);
-  for (int q = 0; q < kp.Ppad; ++q)
-    koff[q / 2] |= ((uint32_t)kp.a[q] | (uint32_t)kp.b[q] << 8) << (16 * (q % 2));
+  // column modes, 8 bits each, in the order a lane half forms them: k-step ks
+  // of kw columns, half h, element e: column kw ks + (split ? 8 h + e : 2 e + h);
+  // two columns per word (a, b, a', b')
+  const int kw = kp.kw, ne = kw / 2;
+  std::vector<uint32_t> modes((size_t)kp.Ppad / 2, 0u);
+  for (int ks = 0; ks < kp.nk; ++ks)
+    for (int h = 0; h < 2; ++h)
+      for (int e = 0; e < ne; ++e) {
+        const int q = kw * ks + (split ? 8 * h + e : 2 * e + h);
+        const size_t word = ((size_t)ks * 2 + h) * (ne / 2) + e / 2;
+        modes[word] |= ((uint32_t)kp.a[q] | (uint32_t)kp.b[q] << 8) << (16 * (e % 2));
+      }
   std::vector<int2> list = g.list;
   if (list.empty()) list.push_back(make_int2(0, 0));
   hipError_t e;
@@ -427,14 +502,14 @@ hipError_t setup_bf16_groups(Plan &pl, const KerrPlan &kp) {
   if ((e = alloc_copy((void **)&pl.gtiles, g.tiles.data(), sizeof(int32_t) * g.tiles.size())) != hipSuccess) return e;
   if ((e = alloc_copy((void **)&pl.glist, list.data(), sizeof(int2) * list.size())) != hipSuccess) return e;
   if ((e = alloc_copy((void **)&pl.grange, g.range.data(), sizeof(int2) * g.range.size())) != hipSuccess) return e;
-  if ((e = alloc_copy((void **)&pl.gkoff, koff.data(), sizeof(uint32_t) * koff.size())) != hipSuccess) return e;
+  if ((e = alloc_copy((void **)&pl.gkoff, modes.data(), sizeof(uint32_t) * modes.size())) != hipSuccess) return e;
   pl.ngroups = g.ngroups;
-  pl.g_tt = TT;
-  pl.kerr_entries[1] = g.blocks * 32.0 * 16.0;
+  pl.g_tt = kTT;
+  pl.kerr_entries[1] = g.blocks * 32.0 * kw;
   return hipSuccess;
 }
 
-hipError_t launch_kerr_bf16(const Plan &pl, double h, const KerrLaunch &k) {
+hipError_t launch_kerr_group(const Plan &pl, double h, const KerrLaunch &k) {
   GArgs a;
   a.src0 = k.src0;
   a.src1 = k.src1;
@@ -443,8 +518,9 @@ hipError_t launch_kerr_bf16(const Plan &pl, double h, const KerrLaunch &k) {
   a.out1 = k.out1;
   a.Ah = (const uint4 *)pl.Sph;
   a.Al = (const uint4 *)pl.Spl;
+  a.A32 = (const float4 *)pl.Sp;
   a.pairs = pl.pairs;
-  a.kmodes = (const int4 *)pl.gkoff;
+  a.kmodes = pl.gkoff;
   a.gtiles = pl.gtiles;
   a.glist = pl.glist;
   a.grange = pl.grange;
@@ -452,12 +528,13 @@ hipError_t launch_kerr_bf16(const Plan &pl, double h, const KerrLaunch &k) {
   a.M = pl.M;
   a.T = pl.T;
   a.P = pl.mfma_rows;
-  a.nk = pl.Ppad / 16;
+  a.nk = pl.Ppad / (pl.precision == MMNLSE_FP32 ? 8 : 16);
   a.ngroups = pl.ngroups;
   a.next = k.next;
   if (pl.T % pl.g_tt != 0) return hipErrorInvalidValue;
   if (pl.precision == MMNLSE_SPLIT_BF16_S) return go_shape<2>(a, k.stage, pl.stream);
-  return go_shape<1>(a, k.stage, pl.stream);
+  if (pl.precision == MMNLSE_SPLIT_BF16) return go_shape<1>(a, k.stage, pl.stream);
+  return go_shape<0>(a, k.stage, pl.stream);
 }
 
 }  // namespace mmnlse

@@ -378,12 +378,11 @@ float bf16_value(uint16_t b) {
 
 }  // namespace
 
-int bf16_group_tile_width(int M, int T);                // kerr_bf16.hip
-hipError_t setup_bf16_groups(Plan &pl, const KerrPlan &kp);
-hipError_t launch_kerr_bf16(const Plan &pl, double h, const KerrLaunch &k);
+hipError_t setup_groups(Plan &pl, const KerrPlan &kp);  // kerr_group.hip
+hipError_t launch_kerr_group(const Plan &pl, double h, const KerrLaunch &k);
 
 hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k) {
-  if (pl.precision != MMNLSE_FP32 && pl.ngroups > 0) return launch_kerr_bf16(pl, h, k);
+  if (pl.ngroups > 0) return launch_kerr_group(pl, h, k);
   MArgs a;
   a.src0 = k.src0;
   a.src1 = k.src1;
@@ -490,11 +489,9 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
   pl.npass = (int)kp.passes.size();
   pl.mfma_rtm = kp.rtm;
   for (int i = 0; i < 3; ++i) pl.kerr_entries[i] = kp.entries[i];
-  // split precisions: the kernel that forms B once per workgroup (kerr_bf16.hip)
-  // where it applies; MMNLSE_SPLIT_KERNEL=passes keeps the per-pass kernel above
-  const char *sk = std::getenv("MMNLSE_SPLIT_KERNEL");
-  if (split && !(sk && std::strcmp(sk, "passes") == 0)) return setup_bf16_groups(pl, kp);
-  return hipSuccess;
+  // the kernel that forms B once per workgroup (kerr_group.hip) where it
+  // applies; MMNLSE_GROUP_KERNEL=0 keeps the per-pass kernel above
+  return setup_groups(pl, kp);
 }
 
 }  // namespace mmnlse

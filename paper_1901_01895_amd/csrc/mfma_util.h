@@ -1,5 +1,5 @@
 // Device helpers shared by the two matrix-core Kerr kernels (kerr_mfma.hip,
-// kerr_bf16.hip): operand conversions, forming B_q = X_l X_m from the LDS
+// kerr_group.hip): operand conversions, forming B_q = X_l X_m from the LDS
 // field tile, and the mode-space scatter of 32x32 accumulator tiles.
 #pragma once
 

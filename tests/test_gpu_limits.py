@@ -145,7 +145,9 @@ def test_kerr_work_counts(gpu_lib, name, kw):
     assert work["nonzero"] == nnz
     plan = mm.kerr_plan(p.S, mm.FP32)
     assert nnz <= work["multiplied"] <= 32 * plan["nrt"] * plan["Ppad"]
-    assert work["multiplied"] == plan["entries"]["multiplied"]
+    # the per-pass kernel multiplies its passes' listed blocks (the host plan's
+    # count); the group kernel only the nonzero (row tile, k-step) blocks
+    assert work["multiplied"] <= plan["entries"]["multiplied"]
     P.close()
 
 
