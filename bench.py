@@ -67,13 +67,13 @@ def kerr_flops_per_eval(M: int, T: int, entries: float | None = None) -> float:
     return 4.0 * entries * T + 6.0 * P * T + 8.0 * M * M * T
 
 
-def linear_bytes_per_apply(M: int, T: int, four_step: bool) -> float:
+def linear_bytes_per_apply(M: int, T: int) -> float:
     """Algorithmic HBM bytes of one half-step propagator application on one
     field: read + write of M*T complex64 plus the M*T hi+lo factor table
-    (16 B per entry).  A four-step transform needs two more read + write
-    passes (the strided column passes)."""
-    passes = 3 if four_step else 1
-    return M * T * (16.0 * passes + 16.0)
+    (16 B per entry), 32 B per sample.  (A four-step transform moves the field
+    through HBM three times, 64 B per sample; that is executed traffic, not
+    the algorithm's.)"""
+    return M * T * 32.0
 
 
 def cpu_model() -> str:
@@ -414,9 +414,9 @@ def _kerr_flops(workload: str, precision: str) -> tuple[float, float]:
 
 def kerr_kernel_precision(name: str):
     """Precision of a matrix-core Kerr kernel from its template arguments
-    (kerr_mfma<W, R, SPLIT, ...>, kerr_bf16<TT, RW, NPART, KC, SPLIT, ...>), else None."""
+    (kerr_mfma<W, R, SPLIT, ...>, kerr_group<TT, RW, NPART, KC, SPLIT, ...>), else None."""
     import re
-    m = re.search(r"kerr_(mfma|bf16)<([^>]*)>", name)
+    m = re.search(r"kerr_(mfma|group)<([^>]*)>", name)
     if not m:
         return None
     args = [a.strip() for a in m.group(2).split(",")]
@@ -553,7 +553,7 @@ def measure(mm, W, p, precision: str, args) -> dict:
     # per-kernel device time (HIP events on the plan's stream), same step count
     B = A0.clone()
     prof = P.profile(B, args.steps)
-    four = p.T > 16384
+    four = p.T > 16384 or (p.T >= 4096 and 2 * p.M < 128)  # the plan's choice of the four-step transform
     kerr_avg_ms = prof["kerr_ms"] / max(prof["kerr_launches"], 1)
     lin_avg_ms = prof["linear_ms"] / max(prof["linear_launches"], 1)
     path = P.kerr_path
@@ -570,7 +570,9 @@ def measure(mm, W, p, precision: str, args) -> dict:
     # RK4IP's linear launches carry two fields (A and k1, then the two stage sums);
     # the split-step schemes transform one field per launch
     fields = 2 if args.method == "rk4ip" else 1
-    lin_gbs = fields * linear_bytes_per_apply(p.M, p.T, four) / (lin_avg_ms * 1e-3) / 1e9
+    # (plans that run whole steps in one workgroup make no separate linear launches)
+    lin_gbs = fields * linear_bytes_per_apply(p.M, p.T) / (lin_avg_ms * 1e-3) / 1e9 if lin_avg_ms > 0 else 0.0
+    lin_exec_gbs = lin_gbs * (2.0 if four else 1.0)
     kerr_dominant = prof["kerr_ms"] >= prof["linear_ms"]
     if kerr_dominant and path == "manakov":
         # pointwise in t with O(M) work per sample: bound by the field passes
@@ -610,12 +612,12 @@ def measure(mm, W, p, precision: str, args) -> dict:
         kname = "linear_half_step"
         roof = {"bound": "hbm", "achieved": lin_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": lin_gbs / HBM_PEAK_GBS, "traffic": traffic_for(kname, args.workload),
-                "kernel": kname, "avg_launch_ms": lin_avg_ms}
+                "kernel": kname, "avg_launch_ms": lin_avg_ms, "executed_GBps": lin_exec_gbs}
     P.close()
     return {"value": value, "ms_per_step": ms_per_step, "roofline": roof, "kerr_kernel": path,
             "kernels": {"kerr_ms_per_step": prof["kerr_ms"] / args.steps, "kerr_executed_tflops": exec_tflops,
                         "linear_ms_per_step": prof["linear_ms"] / args.steps,
-                        "kerr_tflops": kerr_tflops, "linear_GBps": lin_gbs}}
+                        "kerr_tflops": kerr_tflops, "linear_GBps": lin_gbs, "linear_executed_GBps": lin_exec_gbs}}
 
 
 if __name__ == "__main__":
