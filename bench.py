@@ -338,19 +338,19 @@ def serving_report(args) -> dict:
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, precision: str) -> dict:
-    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
-    WRITE_SIZE, ``--precision-only``) into profiles/<kernel>_<workload>_pmc.json.
+    """Turn two rocprofv3 --pmc runs of
+        bench.py --workload <w> --steps K --warmup W --no-cpu-baseline --no-serving
+    (FETCH_SIZE, then WRITE_SIZE) into profiles/kerr_<p>_<w>_pmc.json for
+    precision p: HBM bytes per launch of p's Kerr kernels.
 
     The counters read KiB per dispatch.  Each is scaled by what it reads for
     the plain device-to-device copy of the field that the timed region starts
     with (M*T*8 bytes read and written; the copyBuffer dispatch with the
-    largest reading), and averaged over the dispatches of the dominant Kerr
-    kernel, like the per-launch duration in the roofline.
+    largest reading), and averaged over the dispatches of p's Kerr kernels,
+    like the per-launch duration in the roofline.
     """
     import csv
     import glob
-    import hashlib
-    import re
     import workloads as W
 
     def load(d, counter):
@@ -362,19 +362,19 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, precision: str)
                     out[key] = out.get(key, 0.0) + float(r["Counter_Value"])
         return out
 
-    p = W.make_problem(workload)
-    copy_bytes = float(p.M * p.T * 8)
-    mode = {"fp32": "0", "split_bf16": "1", "split_bf16_s": "2"}[precision]
-    pat = re.compile(r"kerr_mfma<\d+, \d+, " + mode + ",")
+    p = W.make_problem(workload, T=256, n_steps=1)
+    copy_bytes = float(p.M * FULL_T[workload] * 8)
     fe, wr = load(fetch_dir, "FETCH_SIZE"), load(write_dir, "WRITE_SIZE")
-    rec = {"kernel": f"kerr_mfma_{precision}", "workload": workload, "source": "kerr_mfma.hip"}
-    src = os.path.join(ROOT, "paper_1901_01895_amd", "csrc", rec["source"])
-    rec["source_sha256"] = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    rec = {"workload": workload, "precision": precision, "csrc_sha256": csrc_digest(),
+           "command": (f"cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) "
+                       f"--output-format csv -d <dir> -o run -- python3 <repo>/bench.py --workload {workload} "
+                       f"--steps <K> --warmup <W> --no-cpu-baseline --no-serving; python3 bench.py "
+                       f"--summarize-pmc <fetch dir> <write dir> --workload {workload} --precision {precision}")}
     for name, m in (("fetch", fe), ("write", wr)):
         copy = max([v for (_, k), v in m.items() if "copyBuffer" in k] or [0.0])
-        vals = [v for (_, k), v in m.items() if pat.search(k)]
+        vals = [v for (_, k), v in m.items() if kerr_kernel_precision(k) == precision]
         if not copy or not vals:
-            raise SystemExit(f"no {name} counters for the copy or the Kerr kernel under the given folder")
+            raise SystemExit(f"no {name} counters for the copy or the {precision} Kerr kernels under the given folder")
         rec[f"{name}_kib_per_launch"] = sum(vals) / len(vals)
         rec[f"{name}_launches"] = len(vals)
         rec[f"{name}_copy_kib"] = copy
@@ -382,7 +382,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, workload: str, precision: str)
     rec["copy_bytes"] = copy_bytes
     rec["bytes_per_launch"] = 1024.0 * (rec["fetch_kib_per_launch"] * rec["fetch_factor"]
                                         + rec["write_kib_per_launch"] * rec["write_factor"])
-    path = os.path.join(ROOT, "profiles", f"{rec['kernel']}_{workload}_pmc.json")
+    path = os.path.join(ROOT, "profiles", f"kerr_{precision}_{workload}_pmc.json")
     with open(path, "w") as fh:
         json.dump(rec, fh, indent=1)
     return rec
@@ -460,7 +460,9 @@ def summarize_stats(stats_dir: str, workload: str, precision: str, steps: int, w
                        f"--steps {steps} --warmup {warmup}"),
            "rk4ip_steps": total_steps, "kerr_evals": evals,
            "kerr_ms_per_step": kerr_ms / total_steps, "kerr_ms_per_eval": ms_eval,
-           "linear_ms_per_step": sum(r["total_ns"] for r in lin) * 1e-6 / total_steps,
+           # the linear kernels serve every precision the run measured
+           "linear_ms_per_step": sum(r["total_ns"] for r in lin) * 1e-6 / (total_steps * max(1, len(
+               {kerr_kernel_precision(r["name"]) for r in rows} - {None}))),
            "flops_per_eval": flops, "executed_flops_per_eval": xflops,
            "achieved_tflops": flops / (ms_eval * 1e-3) / 1e12,
            "executed_tflops": xflops / (ms_eval * 1e-3) / 1e12,
@@ -473,8 +475,9 @@ def summarize_stats(stats_dir: str, workload: str, precision: str, steps: int, w
 
 
 def summarize_sq(dirs: list[str], workload: str, precision: str) -> dict:
-    """SQ / GRBM counters of the Kerr kernels from rocprofv3 --pmc runs of the
-    bench (one counter set per run) into profiles/kerr_<p>_<w>_sq.json, with
+    """SQ / GRBM counters of precision p's Kerr kernels from rocprofv3 --pmc
+    runs of bench.py --workload <w> --no-cpu-baseline --no-serving (one counter
+    set per run) into profiles/kerr_<p>_<w>_sq.json, with
     per-wave ratios and the matrix-core busy fraction
         SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs * 256 CUs * 4 SIMDs)."""
     import csv
@@ -483,11 +486,16 @@ def summarize_sq(dirs: list[str], workload: str, precision: str) -> dict:
     for d in dirs:
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for r in csv.DictReader(open(f)):
-                if "kerr_" in r["Kernel_Name"]:
+                if kerr_kernel_precision(r["Kernel_Name"]) == precision:
                     tot[r["Counter_Name"]] = tot.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
     if not tot:
         raise SystemExit("no Kerr kernel counters under the given folders")
-    rec = {"workload": workload, "precision": precision, "csrc_sha256": csrc_digest(), "counters": tot}
+    rec = {"workload": workload, "precision": precision, "csrc_sha256": csrc_digest(),
+           "command": ("cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc <counter set> --output-format csv -d <dir> "
+                       f"-o run -- python3 <repo>/bench.py --workload {workload} --steps <K> --warmup <W> "
+                       f"--no-cpu-baseline --no-serving (one run per set); python3 bench.py --summarize-sq <dirs> "
+                       f"--workload {workload} --precision {precision}"),
+           "counters": tot}
     wc = tot.get("SQ_WAVE_CYCLES")
     ratios = {}
     for k in ("SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
@@ -516,18 +524,14 @@ def rocprof_record(workload: str, precision: str):
     return rec if rec.get("csrc_sha256") == csrc_digest() else None
 
 
-def traffic_for(kernel: str, workload: str):
-    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
-    taken on the current kernel source (else None)."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_pmc.json")
+def traffic_for(precision: str, workload: str):
+    """HBM bytes per launch of the Kerr kernels from the committed rocprofv3
+    counter record, if it was taken on the current sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"kerr_{precision}_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_1901_01895_amd", "csrc", rec["source"])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["source_sha256"]:
-        return None
-    return rec["bytes_per_launch"]
+    return rec["bytes_per_launch"] if rec.get("csrc_sha256") == csrc_digest() else None
 
 
 def measure(mm, W, p, precision: str, args) -> dict:
@@ -594,7 +598,7 @@ def measure(mm, W, p, precision: str, args) -> dict:
             bound, peak = "alu", FP32_PEAK_TFLOPS
         kname = f"kerr_{path}_{precision}"
         roof = {"bound": bound, "achieved": kerr_tflops, "peak": peak, "unit": "TFLOP/s",
-                "frac": kerr_tflops / peak, "traffic": traffic_for(kname, args.workload),
+                "frac": kerr_tflops / peak, "traffic": traffic_for(precision, args.workload),
                 "kernel": kname, "avg_launch_ms": kerr_avg_ms,
                 "evals_per_launch": evals_per_launch,
                 "flops_per_eval": kflops, "executed_tflops": exec_tflops,
@@ -611,7 +615,7 @@ def measure(mm, W, p, precision: str, args) -> dict:
     else:
         kname = "linear_half_step"
         roof = {"bound": "hbm", "achieved": lin_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": lin_gbs / HBM_PEAK_GBS, "traffic": traffic_for(kname, args.workload),
+                "frac": lin_gbs / HBM_PEAK_GBS, "traffic": None,
                 "kernel": kname, "avg_launch_ms": lin_avg_ms, "executed_GBps": lin_exec_gbs}
     P.close()
     return {"value": value, "ms_per_step": ms_per_step, "roofline": roof, "kerr_kernel": path,
