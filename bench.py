@@ -131,10 +131,10 @@ def cpu_baseline(p, seconds_target: float = 15.0, method: str = "rk4ip"):
             "one_thread": {"value": p.M * p.T * steps1 / el1, "steps": steps1, "seconds": el1}}
 
 
-def serving(args, precision: str | None = None, rate: float | None = None):
+def serving(args, precision: str | None = None, rate: float | None = None, n_requests: int | None = None):
     """Continuous-batching serving run: seeded Poisson request stream (M in {1,6,15,36},
     T in {2^12,2^14,2^16}, L in {1,10,50} km) submitted at its arrival times.
-    ``precision`` and ``rate`` default to the command line's."""
+    ``precision``, ``rate`` and ``n_requests`` default to the command line's."""
     import threading
 
     import paper_1901_01895_amd as mm
@@ -142,7 +142,7 @@ def serving(args, precision: str | None = None, rate: float | None = None):
 
     precision = precision or args.precision
     rate = args.rate if rate is None and args.workload == "serving" else rate
-    specs = W.serving_stream(args.requests, rate=rate)
+    specs = W.serving_stream(n_requests or args.requests, rate=rate)
     probs = [W.fiber.request_problem(sp) for sp in specs]
     prec = precision_code(mm, precision)
     cfgs = [mm.problem_config(p, precision=prec if p.M > 8 else mm.FP32) for p in probs]
@@ -205,6 +205,8 @@ def main():
                     help="leave out the serving runs of the default report")
     ap.add_argument("--serving-rate", type=float, default=3.6,
                     help="Poisson rate 1/s of the default report's latency runs")
+    ap.add_argument("--serving-requests", type=int, default=128,
+                    help="requests per run of the default report's serving runs")
     ap.add_argument("--full-length", action="store_true",
                     help="run the workload's whole length (L/h steps) in FP32 and split-bf16 and report the FP64 "
                          "power drift and the split-vs-FP32 difference (no throughput line)")
@@ -317,13 +319,14 @@ def full_length(mm, W, p, args) -> dict:
 
 def serving_report(args) -> dict:
     """The serving part of the metric beside the throughput line: the seeded
-    256-request stream saturated (every arrival at t = 0: throughput) and as a
-    Poisson stream at --serving-rate (p50/p99 latency), each with the plain FP32
-    and the split-bf16 contraction.  Progress goes to stderr."""
+    stream of --serving-requests requests saturated (every arrival at t = 0:
+    throughput) and as a Poisson stream at --serving-rate (p50/p99 latency),
+    each with the plain FP32 and the split-bf16 contraction.  Progress goes to
+    stderr."""
     runs = []
     for rate in (None, args.serving_rate):
         for q in ("fp32", "split_bf16"):
-            r = serving(args, precision=q, rate=rate)
+            r = serving(args, precision=q, rate=rate, n_requests=args.serving_requests)
             runs.append({"arrivals": "saturated" if rate is None else f"poisson {rate}/s", "precision": q,
                          "value": r["value"], "unit": r["unit"], "latency_s": r["latency_s"],
                          "wall_s": r["wall_s"], "ticks": r["server"]["rounds"]})
@@ -332,7 +335,7 @@ def serving_report(args) -> dict:
     head = next(r for r in runs if r["arrivals"] != "saturated" and r["precision"] == args.precision
                 ) if args.precision in ("fp32", "split_bf16") else runs[-1]
     sat = next(r for r in runs if r["arrivals"] == "saturated" and r["precision"] == head["precision"])
-    return {"requests": args.requests, "precision": head["precision"], "latency_s": head["latency_s"],
+    return {"requests": args.serving_requests, "precision": head["precision"], "latency_s": head["latency_s"],
             "poisson_rate_per_s": args.serving_rate, "saturated_value": sat["value"], "unit": sat["unit"],
             "runs": runs}
 
