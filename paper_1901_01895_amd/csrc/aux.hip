@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <mutex>
+#include <unordered_map>
 
 #include "common.h"
 
@@ -100,6 +101,27 @@ hipError_t launch_amplify(const Plan &pl, float2 *A) {
   hipLaunchKernelGGL(amplify, dim3(grid_for(n)), dim3(256), 0, pl.stream, A, (const float *)pl.gain, n,
                      pl.logT);
   return hipGetLastError();
+}
+
+hipError_t check_launch(const void *kern, unsigned threads, size_t dyn_lds) {
+  constexpr size_t kLdsPerCu = 160 * 1024;
+  static std::mutex mu;
+  static std::unordered_map<const void *, hipFuncAttributes> cache;
+  hipFuncAttributes at{};
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(kern);
+    if (it != cache.end()) {
+      at = it->second;
+    } else {
+      const hipError_t e = hipFuncGetAttributes(&at, kern);
+      if (e != hipSuccess) return e;
+      cache.emplace(kern, at);
+    }
+  }
+  if (at.maxThreadsPerBlock <= 0 || threads > (unsigned)at.maxThreadsPerBlock) return hipErrorInvalidConfiguration;
+  if (at.sharedSizeBytes + dyn_lds > kLdsPerCu) return hipErrorInvalidConfiguration;
+  return hipSuccess;
 }
 
 int reduction_blocks(size_t n) {

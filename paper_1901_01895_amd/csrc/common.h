@@ -188,6 +188,12 @@ float packed_entry(const float *S, int M, int ar, int br, int aq, int bq);
 // samples per workgroup of the matrix-core kernel for M modes and T samples
 int mfma_tile_width(int M, int T);
 
+// Host-side launch check before a kernel with a large block or dynamic LDS:
+// `threads` within the kernel's compiled limit (launch bounds, registers) and
+// its static LDS plus `dyn_lds` within a CU's 160 KiB.  An oversized
+// configuration returns hipErrorInvalidConfiguration instead of launching.
+hipError_t check_launch(const void *kern, unsigned threads, size_t dyn_lds);
+
 // kernels (launch wrappers); all asynchronous on plan.stream
 hipError_t launch_linear(const Plan &pl, const float4 *E, const float2 *in0, float2 *out0,
                          const float2 *in1, float2 *out1);

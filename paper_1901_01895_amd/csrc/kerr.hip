@@ -319,8 +319,10 @@ hipError_t go_manakov(const KArgs &a, KerrStage st, hipStream_t s) {
   dim3 grid(a.T / TT);
   const size_t shm = (size_t)(st == STAGE_K4 || st == STAGE_K23 ? 2 : 1) * a.M * TT * sizeof(float);
   auto launch = [&](auto kern) -> hipError_t {
+    hipError_t e = check_launch((const void *)kern, TT * GW, shm);
+    if (e != hipSuccess) return e;
     if (shm > 65536) {
-      hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
       if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(kern, grid, dim3(TT * GW), shm, s, a);
@@ -349,27 +351,27 @@ hipError_t go_small(const KArgs &a, KerrStage st, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int STAGE>
-void allow_lds(size_t shm) {
-  if (shm > 65536)
-    (void)hipFuncSetAttribute((const void *)kerr_tiled<STAGE>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-}
-
 hipError_t go_tiled(const KArgs &a, KerrStage st, hipStream_t s) {
   dim3 grid(a.T / TT);
   const size_t shm = (size_t)2 * a.M * TT * sizeof(float2);
-  allow_lds<STAGE_PLAIN>(shm);
-  allow_lds<STAGE_K2>(shm);
-  allow_lds<STAGE_K3>(shm);
-  allow_lds<STAGE_K4>(shm);
+  auto launch = [&](auto kern) -> hipError_t {
+    hipError_t e = check_launch((const void *)kern, TT * GW, shm);
+    if (e != hipSuccess) return e;
+    if (shm > 65536) {
+      e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, grid, dim3(TT * GW), shm, s, a);
+    return hipGetLastError();
+  };
   switch (st) {
-    case STAGE_PLAIN: hipLaunchKernelGGL((kerr_tiled<STAGE_PLAIN>), grid, dim3(TT * GW), shm, s, a); break;
-    case STAGE_K2: hipLaunchKernelGGL((kerr_tiled<STAGE_K2>), grid, dim3(TT * GW), shm, s, a); break;
-    case STAGE_K3: hipLaunchKernelGGL((kerr_tiled<STAGE_K3>), grid, dim3(TT * GW), shm, s, a); break;
-    case STAGE_K4: hipLaunchKernelGGL((kerr_tiled<STAGE_K4>), grid, dim3(TT * GW), shm, s, a); break;
+    case STAGE_PLAIN: return launch(kerr_tiled<STAGE_PLAIN>);
+    case STAGE_K2: return launch(kerr_tiled<STAGE_K2>);
+    case STAGE_K3: return launch(kerr_tiled<STAGE_K3>);
+    case STAGE_K4: return launch(kerr_tiled<STAGE_K4>);
+    default: break;
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -388,9 +390,10 @@ hipError_t launch_manakov_phase(const Plan &pl, double h, const float2 *Az, cons
   a.M = pl.M;
   a.T = pl.T;
   const size_t shm = (size_t)a.M * TT * sizeof(float);
+  hipError_t e = check_launch((const void *)manakov_phase, TT * GW, shm);
+  if (e != hipSuccess) return e;
   if (shm > 65536) {
-    const hipError_t e = hipFuncSetAttribute((const void *)manakov_phase, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)shm);
+    e = hipFuncSetAttribute((const void *)manakov_phase, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(manakov_phase, dim3(a.T / TT), dim3(TT * GW), shm, pl.stream, a);

@@ -421,8 +421,10 @@ hipError_t go(const GArgs &a, KerrStage st, hipStream_t s) {
   const dim3 grid(a.T / TT), block(64 * NW);
   const size_t shm = lds_bytes(a.M, NPART);
   auto launch = [&](auto kern) -> hipError_t {
+    hipError_t e = check_launch((const void *)kern, block.x, shm);
+    if (e != hipSuccess) return e;
     if (shm > 65536) {
-      hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
       if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(kern, grid, block, shm, s, a);
