@@ -48,36 +48,45 @@ struct MArgs {
   int M, T, P, Ppad, next, koff_tt, npass, rtm;  // P: row slots (row tiles x 32)
 };
 
-// One pass over RT consecutive row tiles (rows 32*rt0 .. 32*(rt0+RT)-1) for
-// the wave's 32 samples: accumulate C over all q, then scatter into Os.  The
-// A operand of the next k-step is loaded while the current one is used.
-// A pass's k-list read through registers: lane i of `cur` holds entry 64c + i
-// of chunk c, `nxt` the following chunk (loaded 64 entries before it is
+// A pass's k-list read through registers: lane i of `cur` holds entry
+// base + i, of `nxt` entry base + 64 + i (loaded 64 entries before it is
 // needed).  Entries come out with v_readlane, so the k-loop issues no scalar
 // memory loads (their counter is shared with LDS and would force full waits
 // on the B-operand reads).
 struct KList {
   const int *kl;
-  int len, cur, nxt;
-  __device__ __forceinline__ int load(int c, int lane) const {
-    const int i = 64 * c + lane;
-    return i < len ? kl[i] : 0;
-  }
+  int len, base, cur, nxt;
+  // clamped, so that the load is unconditional (entries past the end are
+  // never used)
+  __device__ __forceinline__ int load(int c, int lane) const { return kl[min(64 * c + lane, len - 1)]; }
   __device__ __forceinline__ void init(const int *k, int n, int lane) {
     kl = k;
     len = n;
+    base = 0;
     cur = load(0, lane);
     nxt = load(1, lane);
   }
-  // entry i, i within the current chunk
-  __device__ __forceinline__ int at(int i) const { return __builtin_amdgcn_readlane(cur, i & 63); }
-  // call when the walk reaches entry i = 64c (c > 0): chunk c becomes current
-  __device__ __forceinline__ void advance(int i, int lane) {
+  // entry i, base <= i < base + 128
+  __device__ __forceinline__ int at(int i) const {
+    const int o = i - base;
+    return o < 64 ? __builtin_amdgcn_readlane(cur, o) : __builtin_amdgcn_readlane(nxt, o - 64);
+  }
+  // the walk has left entries base .. base + 63 behind
+  __device__ __forceinline__ void slide(int lane) {
     cur = nxt;
-    nxt = load((i >> 6) + 1, lane);
+    base += 64;
+    nxt = load(base / 64 + 1, lane);
   }
 };
 
+// One pass over RT consecutive row tiles (rows 32*rt0 .. 32*(rt0+RT)-1) for
+// the wave's 32 samples: accumulate C over the listed k-steps, then scatter
+// into Os.  The k-loop is unrolled by two over two register sets for the A
+// operand and the B offsets: the operands of k-step i + 2 are loaded into
+// the set that k-step i has just used, so every load has a whole k-step to
+// arrive and no registers are copied.  The loads are issued unconditionally
+// (indices clamped into the list), so the compiler counts them instead of
+// waiting for all.
 template <int W, int RT, int SPLIT>
 __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, float2 *Os, int lane, int col,
                                               int rt0, const int *kl, int len) {
@@ -90,91 +99,87 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
     cre[j] = floatx16{0};
     cim[j] = floatx16{0};
   }
+  len = __builtin_amdgcn_readfirstlane(len);
+  const int last = len - 1;
   // The k-loop, for the k-steps kat(0..len-1).  A dense pass walks every
   // k-step in order (kat is the identity, so addresses advance by a stride);
   // a pass with zero blocks reads its list through registers.
   if (!SPLIT) {
     const int nk = a.Ppad / 8;  // 4 k-steps of 2 per iteration (a group of 8 columns)
     const float4 *Ab = a.A32 + (size_t)rt0 * nk * 64 + lane;
-    // this lane half's (oa, ob) for the 4 k-steps of a group; the A operand
-    // and offsets of the next group are loaded one iteration ahead
+    // this lane half's (oa, ob) for the 4 k-steps of a group
     const int4 *ko = a.koff + 2 * half;
-    auto kloop = [&](auto kat) {
-      const int kq0 = kat(0);
-      float4 av[RT], an[RT];
+    auto kloop = [&](auto kat, auto slide) {
+      float4 av[2][RT];
+      int4 o0[2], o1[2];
+      auto load = [&](int set, int kq) {
 #pragma unroll
-      for (int j = 0; j < RT; ++j) an[j] = av[j] = Ab[((size_t)j * nk + kq0) * 64];
-      int4 o0 = ko[4 * kq0], o1 = ko[4 * kq0 + 1], on0 = o0, on1 = o1;
-      for (int it = 0; it < len; ++it) {
-        if (it + 1 < len) {
-          const int kn = kat(it + 1);
-#pragma unroll
-          for (int j = 0; j < RT; ++j) an[j] = Ab[((size_t)j * nk + kn) * 64];
-          on0 = ko[4 * kn];
-          on1 = ko[4 * kn + 1];
-        }
+        for (int j = 0; j < RT; ++j) av[set][j] = Ab[((size_t)j * nk + kq) * 64];
+        o0[set] = ko[4 * kq];
+        o1[set] = ko[4 * kq + 1];
+      };
+      auto body = [&](int set) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-          const int oa = s == 0 ? o0.x : s == 1 ? o0.z : s == 2 ? o1.x : o1.z;
-          const int ob = s == 0 ? o0.y : s == 1 ? o0.w : s == 2 ? o1.y : o1.w;
+          const int oa = s == 0 ? o0[set].x : s == 1 ? o0[set].z : s == 2 ? o1[set].x : o1[set].z;
+          const int ob = s == 0 ? o0[set].y : s == 1 ? o0[set].w : s == 2 ? o1[set].y : o1[set].w;
           const float2 b = form_b(xb, oa, ob);
 #pragma unroll
           for (int j = 0; j < RT; ++j) {
-            const float av_s = s == 0 ? av[j].x : s == 1 ? av[j].y : s == 2 ? av[j].z : av[j].w;
+            const float4 v = av[set][j];
+            const float av_s = s == 0 ? v.x : s == 1 ? v.y : s == 2 ? v.z : v.w;
             cre[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, b.x, cre[j], 0, 0, 0);
             cim[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, b.y, cim[j], 0, 0, 0);
           }
         }
-#pragma unroll
-        for (int j = 0; j < RT; ++j) av[j] = an[j];
-        o0 = on0;
-        o1 = on1;
+      };
+      load(0, kat(0));
+      load(1, kat(min(1, last)));
+      // pairs of k-steps, in chunks of 64 list entries (the list window
+      // slides between chunks); an odd last k-step after the loop
+      for (int c0 = 0; c0 < last; c0 += 64) {
+        const int cend = min(c0 + 64, last);
+        for (int it = c0; it < cend; it += 2) {
+          body(0);
+          load(0, kat(min(it + 2, last)));
+          body(1);
+          load(1, kat(min(it + 3, last)));
+        }
+        slide();
       }
+      if (len & 1) body(0);
     };
     if (len == nk) {
-      kloop([](int i) { return i; });
+      kloop([](int i) { return i; }, [] {});
     } else {
       KList L;
       L.init(kl, len, lane);
-      kloop([&](int i) {
-        if (i > 0 && (i & 63) == 0) L.advance(i, lane);
-        return L.at(i);
-      });
+      kloop([&](int i) { return L.at(i); }, [&] { L.slide(lane); });
     }
   } else {
     const int nk = a.Ppad / 16;  // k-steps of 16
     const uint4 *Hb = a.Ah + (size_t)rt0 * nk * 64 + lane;
     const uint4 *Lb = a.Al + (size_t)rt0 * nk * 64 + lane;
-    // this lane half's (oa, ob) for the 8 pairs of a k-step; operands of the
-    // next k-step one iteration ahead
+    // this lane half's (oa, ob) for the 8 pairs of a k-step
     const int4 *ko = a.koff + 4 * half;
-    auto kloop = [&](auto kat) {
-      const int ks0 = kat(0);
-      uint4 ah[RT], al[RT], ahn[RT], aln[RT];
+    auto kloop = [&](auto kat, auto slide) {
+      uint4 ah[2][RT], al[2][RT];
+      int4 o[2][4];
+      auto load = [&](int set, int ks) {
 #pragma unroll
-      for (int j = 0; j < RT; ++j) {
-        ahn[j] = ah[j] = Hb[((size_t)j * nk + ks0) * 64];
-        aln[j] = al[j] = Lb[((size_t)j * nk + ks0) * 64];
-      }
-      int4 o[4], on[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) on[i] = o[i] = ko[8 * ks0 + i];
-      for (int it = 0; it < len; ++it) {
-        if (it + 1 < len) {
-          const int kn = kat(it + 1);
-#pragma unroll
-          for (int j = 0; j < RT; ++j) {
-            ahn[j] = Hb[((size_t)j * nk + kn) * 64];
-            aln[j] = Lb[((size_t)j * nk + kn) * 64];
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i) on[i] = ko[8 * kn + i];
+        for (int j = 0; j < RT; ++j) {
+          ah[set][j] = Hb[((size_t)j * nk + ks) * 64];
+          al[set][j] = Lb[((size_t)j * nk + ks) * 64];
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o[set][i] = ko[8 * ks + i];
+      };
+      auto body = [&](int set) {
         uint32_t urh[4], url[4], uih[4], uil[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {  // elements 2i and 2i+1
-          const float2 b0 = form_b(xb, o[i].x, o[i].y);
-          const float2 b1 = form_b(xb, o[i].z, o[i].w);
+          const float2 b0 = form_b(xb, o[set][i].x, o[set][i].y);
+          const float2 b1 = form_b(xb, o[set][i].z, o[set][i].w);
           if (SPLIT == 1) {
             split2(b0.x, b1.x, urh[i], url[i]);
             split2(b0.y, b1.y, uih[i], uil[i]);
@@ -190,8 +195,8 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
         const bf16x8 il = __builtin_bit_cast(bf16x8, make_uint4(uil[0], uil[1], uil[2], uil[3]));
 #pragma unroll
         for (int j = 0; j < RT; ++j) {
-          const bf16x8 sh = __builtin_bit_cast(bf16x8, ah[j]);
-          const bf16x8 sl = __builtin_bit_cast(bf16x8, al[j]);
+          const bf16x8 sh = __builtin_bit_cast(bf16x8, ah[set][j]);
+          const bf16x8 sl = __builtin_bit_cast(bf16x8, al[set][j]);
           cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sl, rh, cre[j], 0, 0, 0);
           if (SPLIT == 1) cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rl, cre[j], 0, 0, 0);
           cre[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, rh, cre[j], 0, 0, 0);
@@ -199,24 +204,29 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
           if (SPLIT == 1) cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, il, cim[j], 0, 0, 0);
           cim[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(sh, ih, cim[j], 0, 0, 0);
         }
-#pragma unroll
-        for (int j = 0; j < RT; ++j) {
-          ah[j] = ahn[j];
-          al[j] = aln[j];
+      };
+      load(0, kat(0));
+      load(1, kat(min(1, last)));
+      // pairs of k-steps, in chunks of 64 list entries (the list window
+      // slides between chunks); an odd last k-step after the loop
+      for (int c0 = 0; c0 < last; c0 += 64) {
+        const int cend = min(c0 + 64, last);
+        for (int it = c0; it < cend; it += 2) {
+          body(0);
+          load(0, kat(min(it + 2, last)));
+          body(1);
+          load(1, kat(min(it + 3, last)));
         }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) o[i] = on[i];
+        slide();
       }
+      if (len & 1) body(0);
     };
     if (len == nk) {
-      kloop([](int i) { return i; });
+      kloop([](int i) { return i; }, [] {});
     } else {
       KList L;
       L.init(kl, len, lane);
-      kloop([&](int i) {
-        if (i > 0 && (i & 63) == 0) L.advance(i, lane);
-        return L.at(i);
-      });
+      kloop([&](int i) { return L.at(i); }, [&] { L.slide(lane); });
     }
   }
 #pragma unroll
