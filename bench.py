@@ -581,7 +581,18 @@ def measure(mm, W, p, precision: str, args) -> dict:
     lin_gbs = fields * linear_bytes_per_apply(p.M, p.T) / (lin_avg_ms * 1e-3) / 1e9 if lin_avg_ms > 0 else 0.0
     lin_exec_gbs = lin_gbs * (2.0 if four else 1.0)
     kerr_dominant = prof["kerr_ms"] >= prof["linear_ms"]
-    if kerr_dominant and path == "manakov":
+    solo = prof["linear_launches"] == 0 and args.method == "rk4ip" and p.M == 1
+    if solo:
+        # one mode: whole steps in one workgroup (one launch per call), bound by
+        # one CU's FP32 rate; algorithmic flops per step = 8 transforms of
+        # 5 T log2 T, 4 propagator products and 4 Kerr evaluations of 6 T each
+        sflops = 8 * 5.0 * p.T * math.log2(p.T) + 4 * 2 * 6.0 * p.T + 4 * 8.0 * p.T
+        cu_peak = FP32_PEAK_TFLOPS / 256
+        stf = sflops / (prof["kerr_ms"] / args.steps * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": stf, "peak": cu_peak, "unit": "TFLOP/s", "frac": stf / cu_peak,
+                "traffic": None, "kernel": "rk4ip_solo", "peak_basis": "one CU (one workgroup)",
+                "avg_launch_ms": kerr_avg_ms, "flops_per_step": sflops}
+    elif kerr_dominant and path == "manakov":
         # pointwise in t with O(M) work per sample: bound by the field passes
         # (per step RK4IP's fused K2+K3 and K4 launches read + write 4 fields
         # each, SSFM-RK4 adds the plain k1 launch (2) and its K4 writes one

@@ -311,8 +311,11 @@ mmnlse_status mmnlse_propagate_adaptive(mmnlse_t h, void *A, const mmnlse_adapti
  * ms[0] (Kerr launches) and ms[1] (linear half-step applications; a
  * four-step transform is three kernels timed as one application), with the
  * launch counts in counts[0], counts[1] and the number of Kerr evaluations
- * h N(.) in counts[2].  A is advanced in place.  Errors: E_INVALID,
- * E_DEVICE. */
+ * h N(.) in counts[2].  A one-mode RK4IP plan with 64 <= T <= 2048 (4096
+ * with MMNLSE_SOLO=1 in the environment at create) runs all steps of a call
+ * in one launch of one workgroup; that launch is reported
+ * under ms[0] / counts[0] with no linear launches.  A is advanced in place.
+ * Errors: E_INVALID, E_DEVICE. */
 mmnlse_status mmnlse_profile(mmnlse_t h, void *A, int64_t n_steps, double *ms, int64_t *counts);
 
 /* Wait for all work queued on the handle's stream. */

@@ -220,6 +220,15 @@ hipError_t run_steps(Plan &pl, float2 *A, int64_t n_steps, double h, const float
     }
     return hipSuccess;
   }
+  if (pl.solo) {  // whole steps in one launch; timed as Kerr-class work
+    if (prof && (e = prof->record(prof->kerr, pl.stream)) != hipSuccess) return e;
+    if ((e = launch_rk4ip_solo(pl, A, W0, n_steps, h, E, start, finish)) != hipSuccess) return e;
+    if (prof) {
+      prof->kerr_evals += 4 * n_steps + (start ? 1 : 0) - (finish ? 1 : 0);
+      return prof->record(prof->kerr, pl.stream);
+    }
+    return hipSuccess;
+  }
   if (start) {
     k.stage = STAGE_PLAIN;
     k.src0 = A;
@@ -253,7 +262,7 @@ constexpr int kGraphSteps = 16;
 static bool graph_eligible(const Plan &pl) {
   const char *env = std::getenv("MMNLSE_GRAPH");
   if (env && env[0] == '0') return false;
-  return pl.method == MMNLSE_RK4IP && (size_t)pl.M * pl.T <= ((size_t)1 << 20);
+  return pl.method == MMNLSE_RK4IP && !pl.solo && (size_t)pl.M * pl.T <= ((size_t)1 << 20);
 }
 
 static hipError_t capture_graph(Plan &pl, float2 *A) {
@@ -497,6 +506,22 @@ static mmnlse_status create_impl(const mmnlse_config *cfg, void *stream, mmnlse_
     if (v == KERR_SMALL && M <= 8) pl->kerr_path = KERR_SMALL;
     if (v == KERR_GENERIC) pl->kerr_path = KERR_GENERIC;
     if (v == KERR_MFMA && sym) pl->kerr_path = KERR_MFMA;
+  }
+  // A one-mode RK4IP field of at most 2048 samples runs whole steps in one
+  // workgroup (its Kerr term is pointwise): one launch per call instead of
+  // four to eight per step.  Its transform is the single-pass one, so the
+  // tables are built in natural bin order.  Measured per step, one
+  // workgroup against the launched schedule: T = 256 5.3 vs 13.6 us, 1024
+  // 10.2 vs 17.7, 2048 17.9 vs 25.8, 4096 34.7 vs 26.5 (there the eight
+  // transforms per step on one CU are bound by its LDS bandwidth).
+  // MMNLSE_SOLO=1 also takes T = 4096, MMNLSE_SOLO=0 turns it off.
+  const char *fsolo = std::getenv("MMNLSE_SOLO");
+  const int solo_max = fsolo && fsolo[0] == '1' ? 4096 : 2048;
+  pl->solo = M == 1 && T >= 64 && T <= solo_max && pl->kerr_path == KERR_SMALL && pl->method == MMNLSE_RK4IP &&
+             !(fsolo && fsolo[0] == '0') && !(force4 && force4[0] == '1');
+  if (pl->solo) {
+    pl->four_step = false;
+    pl->N1 = pl->N2 = 0;
   }
   if (pl->kerr_path == KERR_GENERIC && M > 128) {
     free_plan(pl);

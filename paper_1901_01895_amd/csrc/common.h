@@ -94,6 +94,9 @@ struct Plan {
   KerrPath kerr_path = KERR_GENERIC;
   // FFT decomposition: single pass in LDS when !four_step, else T = N1 * N2
   bool four_step = false;
+  // one mode, 64 <= T <= 2048 (4096 on request), RK4IP: whole steps in one
+  // workgroup (rk4ip_solo)
+  bool solo = false;
   int N1 = 0, N2 = 0;
   hipStream_t stream = nullptr;
   int device = 0;
@@ -205,6 +208,10 @@ hipError_t launch_linear_twice(const Plan &pl, const float4 *E, const float2 *in
 // out = DA * exp(i (h gamma / 2) kappa (|Az|^2 + |Aend|^2)) (Manakov form, SSFM-Agrawal)
 hipError_t launch_manakov_phase(const Plan &pl, double h, const float2 *Az, const float2 *Aend,
                                 const float2 *DA, float2 *out);
+// n_steps RK4IP steps of a one-mode plan (pl.solo) in one launch of one
+// workgroup, with run_steps' start / finish contract for N1 = h N(A)
+hipError_t launch_rk4ip_solo(const Plan &pl, float2 *A, float2 *N1, int64_t n_steps, double h, const float4 *E,
+                             bool start, bool finish);
 // E[p][pos] = exp(h/2 L_p)/T (hi + lo) in the FFT's storage order, from beta_d / alpha_d
 hipError_t launch_tabulate_E(const Plan &pl, double h, float4 *E);
 // A[p][:] *= gain[p] in place (the amplifier after a span; needs pl.gain)

@@ -308,6 +308,137 @@ hipError_t single_dispatch(const LinArgs &a, int njobs, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// whole RK4IP steps of a one-mode field in one workgroup (64 <= T <= 4096)
+//
+// With one mode the Kerr term is pointwise, so a step needs nothing from
+// other workgroups.  Thread tid owns samples tid + NT j of the field, of the
+// carried h N(A) and of the RK4 stages, all in registers; the two transforms
+// of each linear half step (A and h N(A), then A_I + k3 and the stage sum)
+// run in LDS as two sequences of one Stockham FFT; the T twiddles are copied
+// to LDS once per launch and each thread keeps the propagator factors of its
+// own bins in registers.  The arithmetic is that of the single-pass linear
+// kernel and kerr_small<1> in the same order (Eq. 6a-f), so one launch for
+// any number of steps gives the same field as the four-launch schedule on
+// the single-pass transform.
+
+struct SoloArgs {
+  float2 *A;         // [T] field, in and out
+  float2 *N1;        // [T] h N(A) carried between calls (read unless start, written unless finish)
+  const float4 *E;   // [T] exp(h/2 L)/T hi + lo, natural bin order
+  const float4 *tw;  // [T] W_T^j hi + lo
+  const float *S;    // S_0000
+  float hg;          // h gamma
+  int n_steps, start, finish;
+};
+
+template <int L>
+constexpr int solo_threads() { return L / 4 < 64 ? 64 : (L / 4 > 1024 ? 1024 : L / 4); }
+
+template <int L, int NT>
+__global__ __launch_bounds__(NT) void rk4ip_solo(SoloArgs a) {
+  constexpr int PT = L / NT;  // samples per thread
+  constexpr int LOG = ilog2c(L);
+  extern __shared__ float4 smem[];
+  float4 *twl = smem;                                  // [L]
+  float2 *buf = reinterpret_cast<float2 *>(smem + L);  // [2][L]
+  const int tid = threadIdx.x;
+  for (int j = tid; j < L; j += NT) twl[j] = a.tw[j];
+  const float s0 = a.S[0];
+  const float hg = a.hg;
+  // i h gamma S |x|^2 x, as eval_small for one mode
+  auto hN = [&](float2 x) -> float2 {
+    float2 am = make_float2(0.f, 0.f);
+    am.x = fmaf(s0, x.x, am.x);
+    am.y = fmaf(s0, x.y, am.y);
+    const float2 an = cfma(make_float2(0.f, 0.f), am, x);
+    const float2 acc = cfma_conj(make_float2(0.f, 0.f), an, x);
+    return make_float2(-hg * acc.y, hg * acc.x);
+  };
+  float4 e[PT];
+  float2 A[PT], N1[PT];
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    const int t = tid + NT * j;
+    e[j] = a.E[t];
+    A[j] = a.A[t];
+    N1[j] = a.start ? hN(A[j]) : a.N1[t];
+  }
+  __syncthreads();
+  // x0 <- D x0, x1 <- D x1
+  auto lin2 = [&](float2 (&x0)[PT], float2 (&x1)[PT]) {
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      buf[tid + NT * j] = x0[j];
+      buf[L + tid + NT * j] = x1[j];
+    }
+    __syncthreads();
+    lds_fft<L, 2, 1, L, NT, false>(buf, twl, LOG);
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      const int f = tid + NT * j;
+      buf[f] = cmul_hilo(buf[f], e[j]);
+      buf[L + f] = cmul_hilo(buf[L + f], e[j]);
+    }
+    __syncthreads();
+    lds_fft<L, 2, 1, L, NT, true>(buf, twl, LOG);
+    // each thread reads back, and next writes, only its own samples: the
+    // next transform's first read of other samples follows a barrier
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      x0[j] = buf[tid + NT * j];
+      x1[j] = buf[L + tid + NT * j];
+    }
+  };
+  for (int s = 0; s < a.n_steps; ++s) {
+    float2 X[PT], K1[PT];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      X[j] = A[j];
+      K1[j] = N1[j];
+    }
+    lin2(X, K1);  // A_I = D A, k1 = D h N(A)
+    float2 Y[PT], Z[PT];
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      const float2 ai = X[j], k1 = K1[j];
+      const float2 k2 = hN(caxpy(ai, 0.5f, k1));
+      const float2 k3 = hN(caxpy(ai, 0.5f, k2));
+      Y[j] = cadd(ai, k3);
+      float2 z = caxpy(ai, 1.f / 6.f, k1);
+      z = caxpy(z, 1.f / 3.f, k2);
+      Z[j] = caxpy(z, 1.f / 3.f, k3);
+    }
+    lin2(Y, Z);  // D (A_I + k3), D (A_I + k1/6 + k2/3 + k3/3)
+    const bool more = s + 1 < a.n_steps || !a.finish;
+#pragma unroll
+    for (int j = 0; j < PT; ++j) {
+      A[j] = caxpy(Z[j], 1.f / 6.f, hN(Y[j]));
+      if (more) N1[j] = hN(A[j]);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PT; ++j) {
+    const int t = tid + NT * j;
+    a.A[t] = A[j];
+    if (!a.finish) a.N1[t] = N1[j];
+  }
+}
+
+template <int L>
+hipError_t go_solo(const SoloArgs &a, hipStream_t s) {
+  constexpr int NT = solo_threads<L>();
+  const size_t shm = (size_t)L * (sizeof(float4) + 2 * sizeof(float2));
+  hipError_t e = check_launch((const void *)rk4ip_solo<L, NT>, NT, shm);
+  if (e != hipSuccess) return e;
+  if (shm > 65536) {
+    e = hipFuncSetAttribute((const void *)rk4ip_solo<L, NT>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((rk4ip_solo<L, NT>), dim3(1), dim3(NT), shm, s, a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_linear(const Plan &pl, const float4 *E, const float2 *in0, float2 *out0,
@@ -361,6 +492,31 @@ hipError_t launch_linear_twice(const Plan &pl, const float4 *E, const float2 *in
   e = rows_dispatch(a, 0, pl.stream);                    // out1 -> out1 (E) and out2 (E twice)
   if (e != hipSuccess) return e;
   return cols_dispatch(a, 2, pl.stream, true);           // both, in place
+}
+
+hipError_t launch_rk4ip_solo(const Plan &pl, float2 *A, float2 *N1, int64_t n_steps, double h, const float4 *E,
+                             bool start, bool finish) {
+  if (!pl.solo || pl.M != 1 || n_steps > INT32_MAX) return hipErrorInvalidValue;
+  SoloArgs a;
+  a.A = A;
+  a.N1 = N1;
+  a.E = E;
+  a.tw = pl.tw;
+  a.S = pl.Sg;
+  a.hg = (float)(h * pl.gamma);
+  a.n_steps = (int)n_steps;
+  a.start = start ? 1 : 0;
+  a.finish = finish ? 1 : 0;
+  switch (pl.T) {
+    case 64: return go_solo<64>(a, pl.stream);
+    case 128: return go_solo<128>(a, pl.stream);
+    case 256: return go_solo<256>(a, pl.stream);
+    case 512: return go_solo<512>(a, pl.stream);
+    case 1024: return go_solo<1024>(a, pl.stream);
+    case 2048: return go_solo<2048>(a, pl.stream);
+    case 4096: return go_solo<4096>(a, pl.stream);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace mmnlse
