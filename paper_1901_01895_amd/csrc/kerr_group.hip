@@ -459,8 +459,10 @@ hipError_t go_shape(const GArgs &a, KerrStage st, hipStream_t s) {
 hipError_t setup_groups(Plan &pl, const KerrPlan &kp) {
   const bool split = pl.precision != MMNLSE_FP32;
   if (group_partials(pl.M) == 0 || pl.T % kTT != 0 || kp.nrt == 0) return hipSuccess;
+  bool force = false;
   if (const char *env = std::getenv("MMNLSE_GROUP_KERNEL")) {
     if (env[0] == '0') return hipSuccess;
+    force = env[0] == '1';
   }
   KerrGroups g;
   plan_groups(kp, NW, group_tiles_per_wave(pl.M), kKC, g);
@@ -472,14 +474,15 @@ hipError_t setup_groups(Plan &pl, const KerrPlan &kp) {
   // whose group blocks are 61 % nonzero: split 2.04 vs 1.72 ms per step,
   // FP32 3.53 vs 2.84).  The group kernel is used when at least 90 % of the
   // blocks of the groups' listed k-steps are nonzero (dense 120-mode tensor:
-  // split 449 -> 297 ms per step, FP32 935 -> 893).
+  // split 449 -> 297 ms per step, FP32 935 -> 893).  MMNLSE_GROUP_KERNEL=1
+  // uses it for every tensor, =0 for none.
   double listed_blocks = 0;
   for (int gi = 0; gi < g.ngroups; ++gi) {
     int n = 0;
     for (int j = 0; j < NW * g.rw; ++j) n += g.tiles[(size_t)gi * NW * g.rw + j] >= 0;
     listed_blocks += (double)g.range[gi].y * n;
   }
-  if (g.blocks < 0.9 * listed_blocks) return hipSuccess;
+  if (!force && g.blocks < 0.9 * listed_blocks) return hipSuccess;
   // column modes, 8 bits each, in the order a lane half forms them: k-step ks
   // of kw columns, half h, element e: column kw ks + (split ? 8 h + e : 2 e + h);
   // two columns per word (a, b, a', b')

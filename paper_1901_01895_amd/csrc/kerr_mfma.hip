@@ -142,8 +142,13 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
         for (int it = c0; it < cend; it += 2) {
           body(0);
           load(0, kat(min(it + 2, last)));
+          // keep the loads a whole k-step ahead of their use (FP32 only: on the
+          // split paths the scheduler's interleaving of one k-step's B
+          // formation with the other's products is worth more)
+          __builtin_amdgcn_sched_barrier(0);
           body(1);
           load(1, kat(min(it + 3, last)));
+          __builtin_amdgcn_sched_barrier(0);
         }
         slide();
       }
