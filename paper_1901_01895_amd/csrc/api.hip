@@ -60,6 +60,7 @@ static hipError_t dev_alloc(Plan &pl, void **p, size_t bytes) {
 static void free_plan(Plan *pl) {
   if (!pl) return;
   hipFree(pl->tw);
+  hipFree(pl->twc);
   hipFree(pl->E);
   hipFree(pl->E2);
   hipFree(pl->Ea);
@@ -404,7 +405,7 @@ void set_last_error(const std::string &msg) { g_err = msg; }
 
 size_t estimate_plan_bytes(const mmnlse_config &cfg) {
   const size_t M = (size_t)cfg.M, T = (size_t)cfg.T, MT = M * T;
-  size_t b = 3 * MT * sizeof(float2) + MT * sizeof(float4) + T * sizeof(float4) + 1024 * sizeof(double2);
+  size_t b = 3 * MT * sizeof(float2) + MT * sizeof(float4) + 2 * T * sizeof(float4) + 1024 * sizeof(double2);
   if (cfg.method == MMNLSE_SSFM_RK4) b += MT * sizeof(float4);
   b += M * (size_t)std::max(0, cfg.n_beta) * sizeof(double) + (cfg.alpha ? M * sizeof(double) : 0);
   if (cfg.span_km > 0) b += M * sizeof(float);
@@ -439,7 +440,7 @@ const char *mmnlse_last_error(void) { return g_err.c_str(); }
 // twiddles, and the generic tensor copy or the packed tensor with its plan.
 static size_t estimate_host_bytes(const mmnlse_config &cfg) {
   const size_t M = (size_t)cfg.M, P = M * (M + 1) / 2;
-  return (size_t)cfg.T * sizeof(float4) + std::max(M * M * M * M * sizeof(float), 5 * P * P + 64 * P);
+  return 2 * (size_t)cfg.T * sizeof(float4) + std::max(M * M * M * M * sizeof(float), 5 * P * P + 64 * P);
 }
 
 static mmnlse_status create_impl(const mmnlse_config *cfg, void *stream, mmnlse_t *out, Plan *&pl_out) {
@@ -539,6 +540,16 @@ static mmnlse_status create_impl(const mmnlse_config *cfg, void *stream, mmnlse_
     }
     if ((e = dev_alloc(*pl, (void **)&pl->tw, sizeof(float4) * T)) != hipSuccess) goto nomem;
     if ((e = hipMemcpy(pl->tw, tw.data(), sizeof(float4) * T, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
+    if (pl->four_step) {  // the column passes' twiddles W_T^(n2 k1), permuted into their access order
+      const int N1 = pl->N1, N2 = pl->N2;
+      std::vector<float4> twc(T);
+      for (int cb = 0; cb < N2 / kFftCols; ++cb)
+        for (int n1 = 0; n1 < N1; ++n1)
+          for (int c = 0; c < kFftCols; ++c)
+            twc[((size_t)cb * N1 + n1) * kFftCols + c] = tw[((size_t)(cb * kFftCols + c) * n1) & (T - 1)];
+      if ((e = dev_alloc(*pl, (void **)&pl->twc, sizeof(float4) * T)) != hipSuccess) goto nomem;
+      if ((e = hipMemcpy(pl->twc, twc.data(), sizeof(float4) * T, hipMemcpyHostToDevice)) != hipSuccess) goto dev;
+    }
   }
   // coefficients, then the propagator tables built from them on the device
   if (cfg->n_beta) {

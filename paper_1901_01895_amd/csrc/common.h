@@ -12,6 +12,9 @@
 
 namespace mmnlse {
 
+// columns per workgroup in the strided (column) passes of the four-step FFT
+constexpr int kFftCols = 16;
+
 // ---------------------------------------------------------------------------
 // device helpers
 // ---------------------------------------------------------------------------
@@ -109,6 +112,8 @@ struct Plan {
 
   // device tables
   float4 *tw = nullptr;   // [T] exp(-2 pi i j / T) as FP32 hi + lo
+  float4 *twc = nullptr;  // four-step: the column passes' twiddles W_T^(n2 k1) in their access
+                          // order, [N2 / kFftCols][N1][kFftCols] (the same values as tw)
   float4 *E = nullptr;    // [M][T] exp(h/2 L)/T as hi + lo, in the FFT's storage order
   float4 *E2 = nullptr;   // same for step 2h, i.e. exp(h L)/T: the split-step's full
                           // linear step and the step-doubling coarse step

@@ -134,6 +134,7 @@ struct LinArgs {
   float2 *out[2];
   const float4 *E;
   const float4 *tw;
+  const float4 *twc;  // four-step column-pass twiddles in access order
   int M, T, logT;
   int N1, N2;
 };
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(NT) void linear_single(LinArgs a) {
 // ---------------------------------------------------------------------------
 // four-step passes
 // ---------------------------------------------------------------------------
-constexpr int COLS = 16;  // columns per workgroup in the strided passes
+constexpr int COLS = kFftCols;  // columns per workgroup in the strided passes
 
 // pass A (INV=false) and pass C (INV=true): C columns of one row
 template <int N1, int NT, bool INV>
@@ -186,13 +187,16 @@ __global__ __launch_bounds__(NT) void linear_cols(LinArgs a) {
   const float2 *__restrict__ in = INV ? a.out[job] : a.in[job];
   float2 *__restrict__ out = a.out[job];
   const size_t rbase = (size_t)row * a.T + c0;
+  // twc[idx] = W_T^((c0 + c) n1) for idx = n1 COLS + c: read in the order of
+  // the samples, 32 contiguous bytes per thread
+  const float4 *__restrict__ twc = a.twc + (size_t)(c0 / COLS) * N1 * COLS;
   for (int idx = 2 * threadIdx.x; idx < N1 * COLS; idx += 2 * NT) {
     const int n1 = idx / COLS, c = idx % COLS;  // c even: columns c, c+1
     const float4 v = ld2(in + rbase + (size_t)n1 * a.N2 + c);
     float2 x0 = make_float2(v.x, v.y), x1 = make_float2(v.z, v.w);
     if (INV) {
-      x0 = cmul_hilo(x0, conj_hilo(a.tw[((c0 + c) * n1) & (a.T - 1)]));
-      x1 = cmul_hilo(x1, conj_hilo(a.tw[((c0 + c + 1) * n1) & (a.T - 1)]));
+      x0 = cmul_hilo(x0, conj_hilo(twc[idx]));
+      x1 = cmul_hilo(x1, conj_hilo(twc[idx + 1]));
     }
     st2(buf + idx, make_float4(x0.x, x0.y, x1.x, x1.y));
   }
@@ -202,9 +206,9 @@ __global__ __launch_bounds__(NT) void linear_cols(LinArgs a) {
     const int k1 = idx / COLS, c = idx % COLS;
     const float4 v = ld2(buf + idx);
     float2 x0 = make_float2(v.x, v.y), x1 = make_float2(v.z, v.w);
-    if (!INV) {
-      x0 = cmul_hilo(x0, a.tw[((c0 + c) * k1) & (a.T - 1)]);
-      x1 = cmul_hilo(x1, a.tw[((c0 + c + 1) * k1) & (a.T - 1)]);
+    if (!INV) {  // k1 in place of n1: twc[k1 COLS + c] = W_T^((c0 + c) k1)
+      x0 = cmul_hilo(x0, twc[idx]);
+      x1 = cmul_hilo(x1, twc[idx + 1]);
     }
     st2(out + rbase + (size_t)k1 * a.N2 + c, make_float4(x0.x, x0.y, x1.x, x1.y));
   }
@@ -450,6 +454,7 @@ hipError_t launch_linear(const Plan &pl, const float4 *E, const float2 *in0, flo
   a.out[1] = out1;
   a.E = E;
   a.tw = pl.tw;
+  a.twc = pl.twc;
   a.M = pl.M;
   a.T = pl.T;
   a.logT = pl.logT;
@@ -482,6 +487,7 @@ hipError_t launch_linear_twice(const Plan &pl, const float4 *E, const float2 *in
   a.out[1] = out2;
   a.E = E;
   a.tw = pl.tw;
+  a.twc = pl.twc;
   a.M = pl.M;
   a.T = pl.T;
   a.logT = pl.logT;
