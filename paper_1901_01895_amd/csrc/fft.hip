@@ -247,6 +247,39 @@ __global__ __launch_bounds__(NT) void linear_rows(LinArgs a) {
     for (int idx = 2 * threadIdx.x; idx < N2 * NB; idx += 2 * NT) st2(a.out[1] + base + idx, ld2(buf2 + idx));
 }
 
+// pass B on both fields of a two-field application in one workgroup: each
+// propagator factor is read once and applied to the same bin of both (the
+// 2 NB rows are transformed as one batch of sequences; per row the
+// arithmetic is that of linear_rows)
+template <int N2, int NB, int NT>
+__global__ __launch_bounds__(NT) void linear_rows_pair(LinArgs a) {
+  __shared__ __align__(16) float2 buf[2 * N2 * NB];
+  __shared__ float4 twl[N2];
+  load_twiddles<N2, NT>(twl, a.tw, a.logT);
+  float2 *__restrict__ io0 = a.out[0];
+  float2 *__restrict__ io1 = a.out[1];
+  const int rows_per_mode = a.N1 / NB;
+  const int mode = blockIdx.x / rows_per_mode;
+  const size_t base = (size_t)mode * a.T + (size_t)(blockIdx.x % rows_per_mode) * NB * N2;
+  for (int idx = 2 * threadIdx.x; idx < N2 * NB; idx += 2 * NT) {
+    st2(buf + idx, ld2(io0 + base + idx));
+    st2(buf + N2 * NB + idx, ld2(io1 + base + idx));
+  }
+  __syncthreads();
+  lds_fft<N2, 2 * NB, 1, N2, NT, false>(buf, twl, ilog2c(N2));
+  for (int idx = threadIdx.x; idx < N2 * NB; idx += NT) {
+    const float4 e = a.E[base + idx];
+    buf[idx] = cmul_hilo(buf[idx], e);
+    buf[N2 * NB + idx] = cmul_hilo(buf[N2 * NB + idx], e);
+  }
+  __syncthreads();
+  lds_fft<N2, 2 * NB, 1, N2, NT, true>(buf, twl, ilog2c(N2));
+  for (int idx = 2 * threadIdx.x; idx < N2 * NB; idx += 2 * NT) {
+    st2(io0 + base + idx, ld2(buf + idx));
+    st2(io1 + base + idx, ld2(buf + N2 * NB + idx));
+  }
+}
+
 template <int L, int NB, int NT>
 hipError_t go_single(const LinArgs &a, int njobs, hipStream_t s) {
   dim3 grid((a.M + NB - 1) / NB, njobs);
@@ -265,8 +298,10 @@ hipError_t go_cols(const LinArgs &a, int njobs, hipStream_t s, bool inv) {
 template <int N2, int NB, int NT>
 hipError_t go_rows(const LinArgs &a, int njobs, hipStream_t s) {
   // njobs == 0: the DUAL form on out[0] (outputs out[0] and out[1])
-  dim3 grid(a.M * (a.N1 / NB), njobs ? njobs : 1);
-  if (njobs) hipLaunchKernelGGL((linear_rows<N2, NB, NT, false>), grid, dim3(NT), 0, s, a);
+  // njobs == 2: both fields in one workgroup (linear_rows_pair)
+  const dim3 grid(a.M * (a.N1 / NB));
+  if (njobs == 2) hipLaunchKernelGGL((linear_rows_pair<N2, NB, NT>), grid, dim3(NT), 0, s, a);
+  else if (njobs == 1) hipLaunchKernelGGL((linear_rows<N2, NB, NT, false>), grid, dim3(NT), 0, s, a);
   else hipLaunchKernelGGL((linear_rows<N2, NB, NT, true>), grid, dim3(NT), 0, s, a);
   return hipGetLastError();
 }
