@@ -74,6 +74,7 @@ static void free_plan(Plan *pl) {
   hipFree(pl->Sph);
   hipFree(pl->Spl);
   hipFree(pl->pairs);
+  hipFree(pl->tile_both);
   hipFree(pl->koff);
   hipFree(pl->passes);
   hipFree(pl->klist);

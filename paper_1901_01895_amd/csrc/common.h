@@ -130,6 +130,7 @@ struct Plan {
   uint16_t *Sph = nullptr;      // bf16 hi of Sp
   uint16_t *Spl = nullptr;      // bf16 lo of Sp - hi
   int32_t *pairs = nullptr;     // [mfma_rows] packed (a | b << 16) of each row slot, -1 = padding
+  uint8_t *tile_both = nullptr; // [row tiles] 1: both lane halves scatter at once (KerrPlan::both)
   int32_t *koff = nullptr;      // [Ppad][2] LDS byte offsets of (X_a, X_b) per q, kernel lane order
   int koff_tt = 0;              // tile width (samples) the offsets were built for
   int4 *passes = nullptr;       // [npass] (first row tile, tiles, k-list offset, k-list length)
@@ -172,6 +173,11 @@ struct KerrPlan {
   std::vector<int4> passes;          // (first row tile, tiles, k-list offset, k-list length)
   std::vector<int32_t> klist;        // k-steps of each pass that hold a nonzero
   std::vector<uint8_t> occ;          // [nrt][nk] 1 where the (row tile, k-step) block holds a nonzero
+  // [nrt] 1 where the tile's rows are placed so that the two lane halves can
+  // scatter at once: the rows in slots 8g + j and 8g + 4 + j (j < 4), which
+  // the halves take together, differ in both modes (p and n) unless one is
+  // padding
+  std::vector<uint8_t> both;
   double entries[3] = {0, 0, 0};     // packed P*P, multiplied, nonzero
 };
 void plan_kerr(const float *S, int M, bool split, KerrPlan &kp);

@@ -41,6 +41,7 @@ struct MArgs {
   const float4 *A32;     // FP32 swizzle: [row tiles][Ppad/8][64] float4
   const uint4 *Ah, *Al;  // bf16 swizzle: [row tiles][Ppad/16][64] 8 x bf16
   const int *pairs;      // [P] per row slot a | b << 16, -1 for a padding row (zero weights)
+  const uint8_t *tboth;  // [row tiles] 1: the lane halves scatter the tile at once
   const int4 *koff;      // B operand: byte offsets of X_a, X_b rows in the LDS tile, lane order
   const int4 *passes;    // [npass] (first row tile, tiles, k-list offset, k-list length)
   const int *klist;      // k-steps of each pass that hold a nonzero entry of its rows
@@ -235,7 +236,12 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
     }
   }
 #pragma unroll
-  for (int j = 0; j < RT; ++j) scatter_tile32<TT>(a.pairs, cre[j], cim[j], rt0 + j, Xs, Os, lane, col);
+  for (int j = 0; j < RT; ++j) {
+    if (__builtin_amdgcn_readfirstlane((int)a.tboth[rt0 + j]))
+      scatter_tile32_both<TT>(a.pairs, cre[j], cim[j], rt0 + j, Xs, Os, lane, col);
+    else
+      scatter_tile32<TT>(a.pairs, cre[j], cim[j], rt0 + j, Xs, Os, lane, col);
+  }
 }
 
 // Full contraction for one wave: the passes of the plan's pass table (runs of
@@ -410,6 +416,7 @@ hipError_t launch_kerr_mfma(const Plan &pl, double h, const KerrLaunch &k) {
   a.Ah = (const uint4 *)pl.Sph;
   a.Al = (const uint4 *)pl.Spl;
   a.pairs = pl.pairs;
+  a.tboth = pl.tile_both;
   a.koff = (const int4 *)pl.koff;
   a.koff_tt = pl.koff_tt;
   a.passes = (const int4 *)pl.passes;
@@ -457,6 +464,7 @@ hipError_t setup_mfma(Plan &pl, const float *S) {
     return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
   };
   if ((e = alloc_copy((void **)&pl.pairs, pairs.data(), sizeof(int32_t) * R)) != hipSuccess) return e;
+  if ((e = alloc_copy((void **)&pl.tile_both, kp.both.data(), sizeof(uint8_t) * nrt)) != hipSuccess) return e;
   // B-operand offsets (bytes into the LDS field tile [M][TT] float2) of X_a and
   // X_b for column q, in the order a lane reads them: split path q = 16 ks +
   // 8 half + e (natural order); FP32 path q = 8 kq + 2 s + half stored at

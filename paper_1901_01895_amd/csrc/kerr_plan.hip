@@ -16,6 +16,7 @@
 // blocks.
 
 #include <algorithm>
+#include <random>
 #include <cstdlib>
 #include <utility>
 #include <vector>
@@ -29,6 +30,76 @@ int mfma_tile_width(int M, int T) { return M <= 64 && T % 128 == 0 ? 128 : 32; }
 float packed_entry(const float *S, int M, int ar, int br, int aq, int bq) {
   const float w = aq < bq ? 2.f : 1.f;
   return w * S[(((size_t)ar * M + aq) * M + bq) * M + br];
+}
+
+// Place the rows of every tile so that both lane halves can scatter at once.
+// In the 32 x 32 MFMA accumulator lane half h holds rows 8g + 4h + j
+// (g, j < 4) of its 32 samples, so at each of its 16 steps the scatter
+// updates the modes of slot 8g + j (half 0) and slot 8g + 4 + j (half 1)
+// in the same instructions.  Rows are matched into 16 such pairs with
+// different p and different n (padding rows match anything), greedily over
+// up to 64 seeded orders; which slot of a tile holds which of its rows does
+// not change the tile's blocks or k-lists.  A tile without such a matching
+// keeps its order and the scatter where the halves take turns.
+static void arrange_tile_rows(KerrPlan &kp) {
+  kp.both.assign(kp.nrt, 0);
+  std::mt19937 rng(20190105u);
+  for (int t = 0; t < kp.nrt; ++t) {
+    const size_t s0 = (size_t)t * 32;
+    std::vector<int> real;
+    for (int i = 0; i < 32; ++i)
+      if (kp.rows[s0 + i] >= 0) real.push_back(i);
+    const int r = (int)real.size();
+    const int need = std::max(0, r - 16);  // real-real pairs needed so the rest fit the padding
+    auto fits = [&](int x, int y) { return kp.ra[s0 + x] != kp.ra[s0 + y] && kp.rb[s0 + x] != kp.rb[s0 + y]; };
+    std::vector<std::pair<int, int>> best;
+    bool ok = false;
+    std::vector<int> order = real;
+    for (int attempt = 0; attempt < 64 && !ok; ++attempt) {
+      if (attempt) std::shuffle(order.begin(), order.end(), rng);
+      std::vector<char> used(32, 0);
+      std::vector<std::pair<int, int>> pr;
+      for (int x : order) {
+        if (used[x]) continue;
+        for (int y : order)
+          if (y != x && !used[y] && fits(x, y)) {
+            used[x] = used[y] = 1;
+            pr.push_back({x, y});
+            break;
+          }
+      }
+      if ((int)pr.size() >= need) {
+        ok = true;
+        best.swap(pr);
+      }
+    }
+    if (!ok) continue;
+    // slot pairs (8g + j, 8g + 4 + j): matched pairs first, then single rows
+    // with padding partners, then padding
+    std::vector<char> placed(32, 0);
+    std::vector<std::pair<int, int>> all = best;
+    for (auto &q : best) placed[q.first] = placed[q.second] = 1;
+    for (int x : real)
+      if (!placed[x]) all.push_back({x, -1});
+    std::vector<int> nrow(32, -1), na(32, 0), nb(32, 0);
+    for (size_t k = 0; k < all.size(); ++k) {
+      const int g = (int)k / 4, j = (int)k % 4;
+      const int sl[2] = {8 * g + j, 8 * g + 4 + j};
+      const int src[2] = {all[k].first, all[k].second};
+      for (int h = 0; h < 2; ++h)
+        if (src[h] >= 0) {
+          nrow[sl[h]] = kp.rows[s0 + src[h]];
+          na[sl[h]] = kp.ra[s0 + src[h]];
+          nb[sl[h]] = kp.rb[s0 + src[h]];
+        }
+    }
+    for (int i = 0; i < 32; ++i) {
+      kp.rows[s0 + i] = nrow[i];
+      kp.ra[s0 + i] = na[i];
+      kp.rb[s0 + i] = nb[i];
+    }
+    kp.both[t] = 1;
+  }
 }
 
 void plan_kerr(const float *S, int M, bool split, KerrPlan &kp) {
@@ -309,6 +380,7 @@ void plan_kerr(const float *S, int M, bool split, KerrPlan &kp) {
   kp.entries[1] = executed;
   kp.entries[2] = nonzero;
   kp.occ.swap(occ);
+  arrange_tile_rows(kp);
 }
 
 void plan_groups(const KerrPlan &kp, int nw, int rw, int kc, KerrGroups &g) {

@@ -184,5 +184,38 @@ __device__ __forceinline__ void scatter_tile32(const int *pairs, const floatx16 
   }
 }
 
+// Scatter of one 32-row tile by both lane halves at once, for tiles whose
+// rows the plan has placed so that the rows the halves take at the same step
+// (slots 8g + j and 8g + 4 + j) differ in p and in n: the read-modify-writes
+// of one instruction then never meet, and each half walks only its own 16
+// rows.  Rows are not merged by p here (the halves' runs differ).
+template <int TT>
+__device__ __forceinline__ void scatter_tile32_both(const int *pairs, const floatx16 &cre, const floatx16 &cim,
+                                                    int rt, const float2 *__restrict__ Xs,
+                                                    float2 *__restrict__ Os, int lane, int col) {
+  const int half = lane >> 5;
+  // this half's slots 8g + 4 half + j: int4 number 2g + half of the tile
+  const int4 *pt = (const int4 *)(pairs + rt * 32) + half;
+  int pr[16];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int4 q = pt[2 * g];
+    pr[4 * g] = q.x;
+    pr[4 * g + 1] = q.y;
+    pr[4 * g + 2] = q.z;
+    pr[4 * g + 3] = q.w;
+  }
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int ab = pr[v];
+    if (ab >= 0) {
+      const int p = ab & 0xffff, n = ab >> 16;
+      const float2 C = make_float2(cre[v], cim[v]);
+      Os[p * TT + col] = cfma_conj(Os[p * TT + col], C, Xs[n * TT + col]);
+      if (p != n) Os[n * TT + col] = cfma_conj(Os[n * TT + col], C, Xs[p * TT + col]);
+    }
+  }
+}
+
 }  // namespace mfma
 }  // namespace mmnlse

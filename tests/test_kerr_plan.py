@@ -80,9 +80,14 @@ def test_dense_tensor_keeps_natural_order_and_full_lists(precision):
     check(plan, Sp)
     assert np.array_equal(plan["perm"][:plan["P"]], np.arange(plan["P"]))
     assert np.all(plan["perm"][plan["P"]:] == -1) and plan["Ppad"] == -(-plan["P"] // 32) * 32
-    # a dense tensor keeps the fixed tiles: rows in order, padding only at the end
+    # a dense tensor keeps the fixed tiles: tile t holds rows 32t .. 32t + 31 (in
+    # the slot order that lets both lane halves scatter at once), padding only in
+    # the last tile
     assert plan["nrt"] == -(-plan["P"] // 32)
-    assert np.array_equal(plan["rows"][:plan["P"]], np.arange(plan["P"]))
+    rows = np.asarray(plan["rows"]).reshape(-1, 32)
+    for t in range(plan["nrt"]):
+        real = sorted(r for r in rows[t] if r >= 0)
+        assert real == list(range(32 * t, min(32 * t + 32, plan["P"])))
     # every k-step holding a real column is listed; all-padding k-steps are not
     nk_real = -(-plan["P"] // plan["kw"])
     assert all(n == nk_real for _, _, _, n in plan["passes"])
@@ -139,3 +144,27 @@ def test_plan_rejects_bad_arguments():
     import paper_1901_01895_amd as mm
     with pytest.raises(mm.MMNLSEError):
         mm.kerr_plan(np.ones((1, 1, 1, 1), np.float32), precision=5)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_masked_tensor_tiles_let_both_lane_halves_scatter(precision):
+    """In the 32 x 32 accumulator lane half h holds rows 8g + 4h + j, so the
+    scatter of both halves at once updates the modes of slots 8g + j and
+    8g + 4 + j in the same instructions.  On the mode-group masked 36-mode
+    tensor the plan places every tile's rows so that those two rows differ in
+    p and in n (or one is padding), which the simultaneous scatter needs."""
+    import paper_1901_01895_amd as mm
+    p = W.make_problem("wdm36", T=2 ** 10, n_steps=1)
+    plan = mm.kerr_plan(p.S, precision)
+    na, nb = [], []
+    for i in range(p.M):
+        for j in range(i, p.M):
+            na.append(i)
+            nb.append(j)
+    rows = np.asarray(plan["rows"]).reshape(-1, 32)
+    for t in range(rows.shape[0]):
+        for g in range(4):
+            for j in range(4):
+                x, y = rows[t, 8 * g + j], rows[t, 8 * g + 4 + j]
+                if x >= 0 and y >= 0:
+                    assert na[x] != na[y] and nb[x] != nb[y], (t, g, j)
