@@ -158,6 +158,57 @@ def test_kerr_term_split_bf16(gpu_lib, M):
     P.close()
 
 
+def _arranged_tiles(mm, S, split):
+    """(tiles, tiles whose slot pairs 8g + j / 8g + 4 + j differ in p and n)."""
+    M = S.shape[0]
+    na, nb = [], []
+    for i in range(M):
+        for j in range(i, M):
+            na.append(i)
+            nb.append(j)
+    rows = np.asarray(mm.kerr_plan(S, split)["rows"]).reshape(-1, 32)
+    ok = 0
+    for t in range(rows.shape[0]):
+        pairs = [(rows[t, 8 * g + j], rows[t, 8 * g + 4 + j]) for g in range(4) for j in range(4)]
+        ok += all(x < 0 or y < 0 or (na[x] != na[y] and nb[x] != nb[y]) for x, y in pairs)
+    return rows.shape[0], ok
+
+
+@pytest.mark.parametrize("kernel", ["pass", "group"])
+@pytest.mark.parametrize("tensor", ["dense20", "dense36", "masked28"])
+def test_kerr_contraction_kernels_and_scatters(gpu_lib, kernel, tensor, monkeypatch):
+    """Both matrix-core kernels forced on dense and mode-group-masked tensors,
+    in all three precisions, against the oracle's definition.  The per-pass
+    kernel scatters tiles whose rows the plan could place for both lane halves
+    at once together and the others in turns; the dense 20- and 36-mode plans
+    hold both kinds (checked on the host), the masked one only the first."""
+    mm = gpu_lib
+    M = int(tensor[-2:])
+    T = 512
+    rng = np.random.default_rng((15, M))
+    if tensor.startswith("dense"):
+        S = W.symmetric_gaussian_tensor(M, rng).astype(np.float32)
+    else:
+        S, _ = W.fiber.coupling_tensor(M, 7, mask_frac=0.7)
+    for split in (0, 1):
+        tiles, ok = _arranged_tiles(mm, S, split)
+        if tensor.startswith("dense"):
+            assert 0 < ok < tiles, (tiles, ok)
+        else:
+            assert ok == tiles, (tiles, ok)
+    monkeypatch.setenv("MMNLSE_GROUP_KERNEL", "0" if kernel == "pass" else "1")
+    X = crandn(rng, M, T)
+    ref = 0.05 * oracle.kerr_term(X.astype(np.complex128), S.astype(np.float64), 1.3)
+    # two products: B rounded once to bf16 (2^-9 relative per product, unbiased)
+    for prec, lo, hi in ((mm.FP32, 0.0, 2e-6), (mm.SPLIT_BF16, 0.0, 3e-5), (mm.SPLIT_BF16_S, 5e-4, 3e-3)):
+        P, _, _ = make(mm, M, T, S=S, gamma=1.3, h=0.05, L=0.05, precision=prec, symmetric=True)
+        assert P.kerr_path == "mfma"
+        err = rel(host(P.kerr(dev(X))), ref)
+        print(f"{kernel} {tensor} precision {prec}: rel L2 {err:.2e}", flush=True)
+        assert lo <= err < hi, (prec, err)
+        P.close()
+
+
 def test_power_reduction(gpu_lib):
     mm = gpu_lib
     P, _, _ = make(mm, 4, 4096)
