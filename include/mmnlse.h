@@ -159,7 +159,24 @@ typedef struct mmnlse_ctx *mmnlse_t;
  * without MMNLSE_S_SYMMETRIC), E_NOMEM (device or host memory; when the
  * environment variable MMNLSE_HOST_BYTES_LIMIT is set, set-ups whose host
  * tables would exceed that many bytes are refused before any device call),
- * E_DEVICE.  Never throws. */
+ * E_DEVICE.  Never throws.
+ * Environment variables read here select among equivalent schedules, for
+ * measurement and tests (results stay within the stated tolerances, and
+ * are bit-identical where noted):
+ *   MMNLSE_FORCE_FOUR_STEP=1|0  four-step transform from T >= 1024 / single
+ *                               pass up to T = 16384
+ *   MMNLSE_KERR_PATH=0|1|2      FP32 Kerr kernel: small-M registers (M <= 8),
+ *                               tiled generic, matrix cores (symmetric S)
+ *   MMNLSE_MFMA_RT=2|4          row tiles per pass of the per-pass kernel
+ *   MMNLSE_GROUP_KERNEL=0|1     never / always the matrix-core kernel that
+ *                               forms B once per workgroup (default: dense
+ *                               tensors only)
+ *   MMNLSE_SOLO=0|1             one-mode fields: never / up to T = 4096 whole
+ *                               steps in one workgroup (default T <= 2048;
+ *                               bit-identical to the launched schedule)
+ *   MMNLSE_GRAPH=0              no step-graph replay (read at each call;
+ *                               bit-identical)
+ *   MMNLSE_HOST_BYTES_LIMIT=n   see E_NOMEM above */
 mmnlse_status mmnlse_create(const mmnlse_config *cfg, void *stream, mmnlse_t *out);
 
 /* Release everything create allocated.  NULL is accepted. */
