@@ -113,18 +113,29 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
     auto kloop = [&](auto kat, auto slide) {
       float4 av[2][RT];
       int4 o0[2], o1[2];
+      float2 xa[2][4], xc[2][4];  // the X_a, X_b of a set's k-step, read one k-step ahead
       auto load = [&](int set, int kq) {
 #pragma unroll
         for (int j = 0; j < RT; ++j) av[set][j] = Ab[((size_t)j * nk + kq) * 64];
         o0[set] = ko[4 * kq];
         o1[set] = ko[4 * kq + 1];
       };
-      auto body = [&](int set) {
+      auto readx = [&](int set) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
           const int oa = s == 0 ? o0[set].x : s == 1 ? o0[set].z : s == 2 ? o1[set].x : o1[set].z;
           const int ob = s == 0 ? o0[set].y : s == 1 ? o0[set].w : s == 2 ? o1[set].y : o1[set].w;
-          const float2 b = form_b(xb, oa, ob);
+          xa[set][s] = *(const float2 *)(xb + oa);
+          xc[set][s] = *(const float2 *)(xb + ob);
+        }
+      };
+      // products of the set's k-step, then the X reads of the other set's
+      // k-step (the next one), which run while these products execute
+      auto body = [&](int set) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const float2 x = xa[set][s], y = xc[set][s];
+          const float2 b = make_float2(fmaf(x.x, y.x, -x.y * y.y), fmaf(x.x, y.y, x.y * y.x));
 #pragma unroll
           for (int j = 0; j < RT; ++j) {
             const float4 v = av[set][j];
@@ -133,19 +144,22 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
             cim[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av_s, b.y, cim[j], 0, 0, 0);
           }
         }
+        readx(1 - set);
       };
       load(0, kat(0));
       load(1, kat(min(1, last)));
+      readx(0);
       // pairs of k-steps, in chunks of 64 list entries (the list window
-      // slides between chunks); an odd last k-step after the loop
+      // slides between chunks); an odd last k-step after the loop.  The
+      // operands are loaded a whole k-step ahead of their use and the X
+      // values one k-step ahead (scheduling barriers keep them there; FP32
+      // only: on the split paths the scheduler's interleaving of one
+      // k-step's B formation with the other's products is worth more).
       for (int c0 = 0; c0 < last; c0 += 64) {
         const int cend = min(c0 + 64, last);
         for (int it = c0; it < cend; it += 2) {
           body(0);
           load(0, kat(min(it + 2, last)));
-          // keep the loads a whole k-step ahead of their use (FP32 only: on the
-          // split paths the scheduler's interleaving of one k-step's B
-          // formation with the other's products is worth more)
           __builtin_amdgcn_sched_barrier(0);
           body(1);
           load(1, kat(min(it + 3, last)));
