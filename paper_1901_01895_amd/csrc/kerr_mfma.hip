@@ -194,12 +194,27 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
 #pragma unroll
         for (int i = 0; i < 4; ++i) o[set][i] = ko[8 * ks + i];
       };
+      float2 xr[4][4];  // X_a, X_b of the next k-step's elements 2i, 2i+1, read ahead
+      auto readx = [&](int set) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          xr[i][0] = *(const float2 *)(xb + o[set][i].x);
+          xr[i][1] = *(const float2 *)(xb + o[set][i].y);
+          xr[i][2] = *(const float2 *)(xb + o[set][i].z);
+          xr[i][3] = *(const float2 *)(xb + o[set][i].w);
+        }
+      };
+      auto cmulx = [](float2 x, float2 y) {
+        return make_float2(fmaf(x.x, y.x, -x.y * y.y), fmaf(x.x, y.y, x.y * y.x));
+      };
+      // B of the set's k-step from the X values read ahead, then the reads of
+      // the next k-step (the other set's offsets), then the products
       auto body = [&](int set) {
         uint32_t urh[4], url[4], uih[4], uil[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {  // elements 2i and 2i+1
-          const float2 b0 = form_b(xb, o[set][i].x, o[set][i].y);
-          const float2 b1 = form_b(xb, o[set][i].z, o[set][i].w);
+          const float2 b0 = cmulx(xr[i][0], xr[i][1]);
+          const float2 b1 = cmulx(xr[i][2], xr[i][3]);
           if (SPLIT == 1) {
             split2(b0.x, b1.x, urh[i], url[i]);
             split2(b0.y, b1.y, uih[i], uil[i]);
@@ -213,6 +228,7 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
         const bf16x8 rl = __builtin_bit_cast(bf16x8, make_uint4(url[0], url[1], url[2], url[3]));
         const bf16x8 ih = __builtin_bit_cast(bf16x8, make_uint4(uih[0], uih[1], uih[2], uih[3]));
         const bf16x8 il = __builtin_bit_cast(bf16x8, make_uint4(uil[0], uil[1], uil[2], uil[3]));
+        readx(1 - set);
 #pragma unroll
         for (int j = 0; j < RT; ++j) {
           const bf16x8 sh = __builtin_bit_cast(bf16x8, ah[set][j]);
@@ -227,6 +243,7 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
       };
       load(0, kat(0));
       load(1, kat(min(1, last)));
+      readx(0);
       // pairs of k-steps, in chunks of 64 list entries (the list window
       // slides between chunks); an odd last k-step after the loop
       for (int c0 = 0; c0 < last; c0 += 64) {
