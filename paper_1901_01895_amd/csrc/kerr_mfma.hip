@@ -251,8 +251,12 @@ __device__ __forceinline__ void contract_pass(const MArgs &a, const float2 *Xs, 
         for (int it = c0; it < cend; it += 2) {
           body(0);
           load(0, kat(min(it + 2, last)));
+          // the operand loads stay a k-step ahead; every other kind of
+          // instruction may still be interleaved across the two k-steps
+          __builtin_amdgcn_sched_barrier(0x038F);
           body(1);
           load(1, kat(min(it + 3, last)));
+          __builtin_amdgcn_sched_barrier(0x038F);
         }
         slide();
       }
